@@ -1,0 +1,124 @@
+"""CPU oracle of the matrix-form LIF simulation with synaptic delays.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``.  The product (the HIP library and
+its binding) never imports, links or runs anything here.
+
+The computation lives in ``lif_oracle.c`` (plain C, double precision, one
+thread); this module compiles it with gcc and marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lif_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OR_OK = 0
+OR_NONEXACT = -6
+
+
+def build(src: str = SRC, out: str = LIB, extra_flags=()) -> str:
+    """Compile the oracle (always recompiles)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-Wall", *extra_flags, "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_P = ctypes.c_void_p
+
+
+def _bind(lib):
+    lib.or_lif_sparse.restype = ctypes.c_int
+    lib.or_lif_sparse.argtypes = [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
+                                  _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int]
+    lib.or_lif_dense.restype = ctypes.c_int
+    lib.or_lif_dense.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P,
+                                 _P, _P, _P, _P, _P, ctypes.c_int]
+    return lib
+
+
+@dataclasses.dataclass
+class OracleResult:
+    spikes: np.ndarray      # uint8 [B][T][N]
+    V: np.ndarray           # float64 [B][N], state after the last step
+    ref: np.ndarray         # int32 [B][N], refractory steps left
+    exact: bool             # every partial sum provably exact in binary32
+
+
+class Oracle:
+    def __init__(self, path: Optional[str] = None):
+        path = path or LIB
+        if not os.path.exists(path):
+            build(out=path)
+        self.lib = _bind(ctypes.CDLL(path))
+
+    @staticmethod
+    def _ptr(a: np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+
+    def _params(self, net):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        return (f(net.threshold), f(net.leak), f(net.reset),
+                np.ascontiguousarray(net.refractory, dtype=np.int32), f(net.amplitude))
+
+    def run_sparse(self, net, steps: Optional[int] = None, trials=None) -> OracleResult:
+        """Simulate ``net`` through its COO synapse list for ``steps`` steps
+        (default: all), for all trials or the listed trial indices."""
+        T = net.steps if steps is None else int(steps)
+        ext = net.ext[:, :T] if trials is None else net.ext[list(trials), :T]
+        ext = np.ascontiguousarray(ext, dtype=np.uint8)
+        B, N = ext.shape[0], net.n
+        th, lk, rs, rf, am = self._params(net)
+        pre = np.ascontiguousarray(net.pre, dtype=np.int32)
+        post = np.ascontiguousarray(net.post, dtype=np.int32)
+        w = np.ascontiguousarray(net.weight, dtype=np.float64)
+        d = np.ascontiguousarray(net.delay, dtype=np.int32)
+        spikes = np.zeros((B, T, N), np.uint8)
+        V = np.zeros((B, N), np.float64)
+        ref = np.zeros((B, N), np.int32)
+        P = self._ptr
+        rc = self.lib.or_lif_sparse(N, B, int(net.max_delay), T, P(th), P(lk), P(rs), P(rf), P(am),
+                                    pre.shape[0], P(pre), P(post), P(w), P(d),
+                                    P(ext), P(spikes), P(V), P(ref), 1)
+        if rc not in (OR_OK, OR_NONEXACT):
+            raise ValueError(f"oracle rejected the input (status {rc})")
+        return OracleResult(spikes, V, ref, rc == OR_OK)
+
+    def run_dense(self, net, steps: Optional[int] = None, trials=None) -> OracleResult:
+        """Simulate ``net`` through its dense weight matrix (delay 1)."""
+        assert net.dense_weight is not None
+        T = net.steps if steps is None else int(steps)
+        ext = net.ext[:, :T] if trials is None else net.ext[list(trials), :T]
+        ext = np.ascontiguousarray(ext, dtype=np.uint8)
+        B, N = ext.shape[0], net.n
+        th, lk, rs, rf, am = self._params(net)
+        W = np.ascontiguousarray(net.dense_weight, dtype=np.float64)
+        spikes = np.zeros((B, T, N), np.uint8)
+        V = np.zeros((B, N), np.float64)
+        ref = np.zeros((B, N), np.int32)
+        P = self._ptr
+        rc = self.lib.or_lif_dense(N, B, T, P(th), P(lk), P(rs), P(rf), P(am), P(W),
+                                   P(ext), P(spikes), P(V), P(ref), 1)
+        if rc not in (OR_OK, OR_NONEXACT):
+            raise ValueError(f"oracle rejected the input (status {rc})")
+        return OracleResult(spikes, V, ref, rc == OR_OK)
+
+
+_default: Optional[Oracle] = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default

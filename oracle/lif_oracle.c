@@ -1,0 +1,225 @@
+/*
+ * CPU oracle for the homogeneous (matrix-form, "MAT") leaky integrate-and-fire
+ * simulation with synaptic delays of SuperNeuro (Date et al., ICONS'23, §2.1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference
+ * that the GPU path is checked against.  Only the test-suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header or table with the HIP library; the product never calls it.
+ *
+ * Arithmetic is IEEE double.  The workloads use dyadic values (multiples of
+ * 2^-6) whose every partial sum stays far below 2^17, so every sum below is
+ * exact in double and in float alike, in any order.  With check_exact != 0 the
+ * oracle verifies that premise step by step and returns OR_NONEXACT when it
+ * fails (the computed result is still written out).
+ *
+ * Model, per trial b, neuron j, step t = 0 .. T-1 (state of step -1: V = r,
+ * refractory counter 0, no spikes):
+ *   1. constant leak towards the reset state r (§2.1, leak paragraph): above r
+ *      subtract lambda, below r add lambda, never crossing r;
+ *   2. add the spikes of earlier steps through the weight matrix, a synapse
+ *      i->j of weight w and integer delay d >= 1 delivering w at t when i
+ *      spiked at t-d (§2.1: W row = pre, column = post; delay d realised in
+ *      the paper by a chain of d-1 unit-delay proxy neurons);
+ *   3. add the external spikes of step t, scaled by the amplitude a_j;
+ *   4. spike candidate c = (U > threshold)  (strict: the ABM description in
+ *      §2.2 states "greater than", and the leak notion is shared);
+ *   5. refractory period: a neuron whose counter is non-zero has its spike
+ *      zeroed and its counter decremented (§2.1, last step);
+ *   6. an emitted spike resets the state to r and starts a refractory window
+ *      of R steps (reset state and refractory period are the neuron
+ *      parameters listed in §2.1).
+ * A suppressed (refractory) super-threshold neuron keeps U: only its spike is
+ * removed.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+#define OR_NONEXACT (-6)
+
+/* 2^17: bound on |partial sum| that keeps multiples of 2^-6 exact in binary32
+ * (2^17 / 2^-6 = 2^23 < 2^24). */
+static const double EXACT_LIMIT = 131072.0;
+
+/* Is x a finite multiple of 2^-6 below the exactness limit? */
+static int on_grid(double x) {
+    if (!isfinite(x) || fabs(x) >= EXACT_LIMIT) return 0;
+    double s = x * 64.0;
+    return s == floor(s);
+}
+
+/* Step 1: constant leak towards r, never crossing it (§2.1). */
+static double apply_leak(double v, double r, double lambda) {
+    if (v > r) {
+        double u = v - lambda;
+        return u < r ? r : u;
+    }
+    if (v < r) {
+        double u = v + lambda;
+        return u > r ? r : u;
+    }
+    return v;
+}
+
+/* Steps 4-6 for one neuron; returns the emitted spike (0/1) and updates
+ * *v (new state) and *ref (remaining refractory steps). */
+static int fire_and_reset(double u, double theta, double r, int32_t R,
+                          double* v, int32_t* ref) {
+    int candidate = u > theta;                /* step 4 */
+    int spike;
+    if (*ref > 0) {                           /* step 5 */
+        spike = 0;
+        *ref = *ref - 1;
+    } else {
+        spike = candidate;
+    }
+    if (spike) {                              /* step 6 */
+        *v = r;
+        *ref = R;
+    } else {
+        *v = u;
+    }
+    return spike;
+}
+
+static int check_params(int32_t N, const double* theta, const double* leak,
+                        const double* reset, const int32_t* refractory,
+                        const double* amplitude) {
+    for (int32_t j = 0; j < N; ++j) {
+        if (!on_grid(theta[j]) || !on_grid(reset[j]) || !on_grid(amplitude[j]))
+            return 0;
+        if (!(leak[j] >= 0.0)) return 0;
+        if (!isinf(leak[j]) && !on_grid(leak[j])) return 0;
+        if (refractory[j] < 0) return 0;
+    }
+    return 1;
+}
+
+/*
+ * Sparse synapse list (COO: pre[k] -> post[k], weight w[k], delay delay[k]).
+ * ext and spikes are byte arrays [B][T][N] holding 0 or 1.
+ * V_out [B][N] and ref_out [B][N] receive the state after step T-1.
+ */
+int or_lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
+                  const double* theta, const double* leak, const double* reset,
+                  const int32_t* refractory, const double* amplitude,
+                  int64_t nnz, const int32_t* pre, const int32_t* post,
+                  const double* w, const int32_t* delay,
+                  const uint8_t* ext, uint8_t* spikes,
+                  double* V_out, int32_t* ref_out, int check_exact) {
+    if (N < 1 || B < 1 || D < 1 || T < 0 || nnz < 0) return OR_EINVAL;
+    for (int64_t k = 0; k < nnz; ++k) {
+        if (pre[k] < 0 || pre[k] >= N || post[k] < 0 || post[k] >= N) return OR_EINVAL;
+        if (delay[k] < 1 || delay[k] > D) return OR_EINVAL;
+        if (!isfinite(w[k])) return OR_EINVAL;
+    }
+    int exact = 1;
+    if (check_exact) {
+        if (!check_params(N, theta, leak, reset, refractory, amplitude)) exact = 0;
+        for (int64_t k = 0; k < nnz; ++k)
+            if (!on_grid(w[k])) exact = 0;
+    }
+    /* in_abs[j] = sum of |w| over synapses into j: bounds the synaptic term. */
+    double* in_abs = (double*)calloc((size_t)N, sizeof(double));
+    double* U = (double*)malloc((size_t)N * sizeof(double));
+    if (!in_abs || !U) { free(in_abs); free(U); return OR_ENOMEM; }
+    for (int64_t k = 0; k < nnz; ++k) in_abs[post[k]] += fabs(w[k]);
+
+    for (int32_t b = 0; b < B; ++b) {
+        double* V = V_out + (size_t)b * N;
+        int32_t* ref = ref_out + (size_t)b * N;
+        const uint8_t* xb = ext + (size_t)b * T * N;
+        uint8_t* sb = spikes + (size_t)b * T * N;
+        for (int32_t j = 0; j < N; ++j) { V[j] = reset[j]; ref[j] = 0; }
+
+        for (int32_t t = 0; t < T; ++t) {
+            /* 1. leak */
+            for (int32_t j = 0; j < N; ++j) {
+                U[j] = apply_leak(V[j], reset[j], leak[j]);
+                if (check_exact && !(fabs(U[j]) + in_abs[j] + fabs(amplitude[j]) < EXACT_LIMIT))
+                    exact = 0;
+            }
+            /* 2. delayed synaptic input: w * s_pre(t - d) */
+            for (int64_t k = 0; k < nnz; ++k) {
+                int32_t src_t = t - delay[k];
+                if (src_t < 0) continue;
+                if (sb[(size_t)src_t * N + pre[k]]) U[post[k]] += w[k];
+            }
+            /* 3. external spikes */
+            for (int32_t j = 0; j < N; ++j)
+                if (xb[(size_t)t * N + j]) U[j] += amplitude[j];
+            /* 4-6. threshold, refractory, reset */
+            for (int32_t j = 0; j < N; ++j)
+                sb[(size_t)t * N + j] =
+                    (uint8_t)fire_and_reset(U[j], theta[j], reset[j], refractory[j], &V[j], &ref[j]);
+        }
+    }
+    free(in_abs);
+    free(U);
+    return exact ? OR_OK : OR_NONEXACT;
+}
+
+/*
+ * Dense weight matrix W [N][N] (row = pre, column = post, §2.1), every synapse
+ * of delay 1: the literal matrix form "spike vector of the previous step times
+ * the weight matrix".  Same state layout as or_lif_sparse.
+ */
+int or_lif_dense(int32_t N, int32_t B, int32_t T,
+                 const double* theta, const double* leak, const double* reset,
+                 const int32_t* refractory, const double* amplitude,
+                 const double* W, const uint8_t* ext, uint8_t* spikes,
+                 double* V_out, int32_t* ref_out, int check_exact) {
+    if (N < 1 || B < 1 || T < 0) return OR_EINVAL;
+    int exact = 1;
+    if (check_exact) {
+        if (!check_params(N, theta, leak, reset, refractory, amplitude)) exact = 0;
+    }
+    double* in_abs = (double*)calloc((size_t)N, sizeof(double));
+    double* U = (double*)malloc((size_t)N * sizeof(double));
+    if (!in_abs || !U) { free(in_abs); free(U); return OR_ENOMEM; }
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t j = 0; j < N; ++j) {
+            double x = W[(size_t)i * N + j];
+            if (!isfinite(x)) { free(in_abs); free(U); return OR_EINVAL; }
+            if (check_exact && x != 0.0 && !on_grid(x)) exact = 0;
+            in_abs[j] += fabs(x);
+        }
+
+    for (int32_t b = 0; b < B; ++b) {
+        double* V = V_out + (size_t)b * N;
+        int32_t* ref = ref_out + (size_t)b * N;
+        const uint8_t* xb = ext + (size_t)b * T * N;
+        uint8_t* sb = spikes + (size_t)b * T * N;
+        for (int32_t j = 0; j < N; ++j) { V[j] = reset[j]; ref[j] = 0; }
+
+        for (int32_t t = 0; t < T; ++t) {
+            for (int32_t j = 0; j < N; ++j) {
+                U[j] = apply_leak(V[j], reset[j], leak[j]);
+                if (check_exact && !(fabs(U[j]) + in_abs[j] + fabs(amplitude[j]) < EXACT_LIMIT))
+                    exact = 0;
+            }
+            /* s(t-1) x W: a zero spike contributes exactly nothing */
+            if (t > 0) {
+                const uint8_t* sp = sb + (size_t)(t - 1) * N;
+                for (int32_t i = 0; i < N; ++i) {
+                    if (!sp[i]) continue;
+                    const double* row = W + (size_t)i * N;
+                    for (int32_t j = 0; j < N; ++j) U[j] += row[j];
+                }
+            }
+            for (int32_t j = 0; j < N; ++j)
+                if (xb[(size_t)t * N + j]) U[j] += amplitude[j];
+            for (int32_t j = 0; j < N; ++j)
+                sb[(size_t)t * N + j] =
+                    (uint8_t)fire_and_reset(U[j], theta[j], reset[j], refractory[j], &V[j], &ref[j]);
+        }
+    }
+    free(in_abs);
+    free(U);
+    return exact ? OR_OK : OR_NONEXACT;
+}
