@@ -1,0 +1,199 @@
+/*
+ * superneuro_mi.h -- C ABI of an MI355X (gfx950) library that simulates
+ * homogeneous networks of leaky integrate-and-fire neurons with synaptic
+ * delays in the matrix form of SuperNeuro (Date et al., ICONS'23, §2.1).
+ *
+ * Model (§2.1).  Every neuron j carries four parameters -- threshold theta_j,
+ * leak lambda_j, reset state r_j, refractory period R_j -- plus the amplitude
+ * a_j of an external spike.  Parameters and state are vectors over neurons.
+ * A synapse i -> j carries a weight w (entry (i, j) of the weight matrix:
+ * row = pre-neuron, column = post-neuron) and an integer delay d >= 1; the
+ * paper realises d > 1 with d-1 unit-delay relay neurons, this library with a
+ * spike history, which yields the same spike times.  Step t, for every
+ * neuron, using only spikes of steps < t and the external spikes of step t:
+ *   1. leak: U = V(t-1) moved towards r_j by lambda_j without crossing r_j;
+ *   2. synaptic input: U += sum of w over synapses whose pre-neuron spiked at
+ *      t - d;
+ *   3. external input: U += a_j if neuron j has an external spike at t;
+ *   4. candidate spike: U > theta_j (strictly greater);
+ *   5. refractory: while the refractory counter is non-zero the spike is
+ *      suppressed and the counter decremented;
+ *   6. reset: an emitted spike sets V = r_j and the counter to R_j;
+ *      otherwise V = U.
+ * Initial state (and after sn_reset_state): V = r, counters 0, no spikes.
+ *
+ * Numbers.  State and arithmetic are IEEE binary32.  When every weight,
+ * threshold, leak, reset and amplitude is a multiple of 2^-6 and every
+ * partial sum stays below 2^17 in magnitude, all sums are exact, so results
+ * do not depend on summation order and match any exact reference bit for bit.
+ *
+ * Threading.  A network object may be used from one host thread at a time.
+ * All device work of a network is issued on the stream given at creation.
+ *
+ * Errors.  Every call returns SN_OK (0) or a negative sn_status; no C++
+ * exception crosses this interface.  sn_last_error() returns a thread-local
+ * message describing the most recent failure of the calling thread.
+ * Validation failures (SN_EINVAL, SN_ERANGE, SN_EINEXACT) leave the network
+ * unchanged.  A failed HIP call returns SN_EDEVICE and poisons the network:
+ * every later call on it except sn_destroy_network returns SN_ESTATE.
+ */
+#ifndef SUPERNEURO_MI_H
+#define SUPERNEURO_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sn_status;
+enum {
+  SN_OK = 0,
+  SN_EINVAL = -1,    /* malformed argument (null pointer, bad size, non-finite value) */
+  SN_ENOMEM = -2,    /* device or host allocation failed */
+  SN_EDEVICE = -3,   /* a HIP call failed; the network is poisoned */
+  SN_ESTATE = -4,    /* call out of order, or network poisoned earlier */
+  SN_ERANGE = -5,    /* index, delay, size or step outside the supported range */
+  SN_EINEXACT = -6   /* a dense weight is not exactly representable in bfloat16 */
+};
+
+/* Limits of this build. */
+#define SN_MAX_NEURONS (1 << 20)  /* pre-neuron index packs into 20 bits */
+#define SN_MAX_DELAY 64           /* delay - 1 packs into 6 bits */
+
+/* Delivery / execution strategies (sn_set_path).  AUTO picks one from the
+ * network's size, density and trial count; the others force one, for
+ * benchmarking and testing.  Every strategy computes identical results. */
+enum {
+  SN_PATH_AUTO = 0,
+  SN_PATH_SMALL = 1,    /* one workgroup per trial runs all requested steps in one launch */
+  SN_PATH_STEP = 2,     /* one launch per step: pull delivery over post-neuron groups */
+  SN_PATH_PERSIST = 3,  /* one cooperative launch for all steps, grid barrier per step */
+  SN_PATH_DENSE = 4     /* dense weights on matrix cores (needs sn_load_dense_weights) */
+};
+
+/* Device-memory allocator.  alloc returns device memory of at least `bytes`
+ * bytes (256-byte aligned) or NULL; free releases it.  Both are called only
+ * from the thread that calls into the library.  A NULL allocator means
+ * hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} sn_allocator;
+
+/* Neuron population (§2.1: threshold, leak, reset state and refractory
+ * period per neuron, plus the external-spike amplitude).  Each per-neuron
+ * array is optional: NULL selects the matching *_scalar for every neuron.
+ * Arrays are host memory of n_neurons elements, read during the call only.
+ * Requirements: thresholds, resets and amplitudes finite; leaks >= 0
+ * (+infinity allowed: the state returns to r every step, as the paper's
+ * relay neurons); refractory periods 0..255. */
+typedef struct {
+  int32_t n_neurons;          /* N, 1 .. SN_MAX_NEURONS */
+  int32_t n_trials;           /* B >= 1 independent copies of the state and inputs, sharing weights and parameters */
+  int32_t max_delay;          /* D, 1 .. SN_MAX_DELAY: largest synaptic delay that will be loaded */
+  const float* threshold;
+  const float* leak;
+  const float* reset;
+  const uint8_t* refractory;
+  const float* amplitude;
+  float threshold_scalar;
+  float leak_scalar;
+  float reset_scalar;
+  float amplitude_scalar;
+  uint8_t refractory_scalar;
+} sn_net_desc;
+
+typedef struct sn_net sn_net;
+
+/* Creates a network on the current HIP device.  `hip_stream` is a
+ * hipStream_t (NULL: the null stream); all device work of the network is
+ * ordered on it.  `alloc` may be NULL (see sn_allocator).  On success *out
+ * owns every device buffer it allocates; the state is the initial state.
+ * Errors: SN_EINVAL (null desc/out, non-finite parameter, negative leak),
+ * SN_ERANGE (N, B or D outside the limits), SN_ENOMEM, SN_EDEVICE. */
+sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc,
+                            void* hip_stream, sn_net** out);
+
+/* Loads the synapses as a host COO list of nnz entries (§2.1: weight and
+ * delay per synapse, W[pre][post]).  pre/post in [0, N), w finite,
+ * delay in [1, D].  Duplicate (pre, post) pairs act as separate synapses
+ * (their weights add); self-synapses are allowed.  nnz may be 0.  Replaces
+ * any earlier synapses; the simulation state is kept.  Arrays are read during
+ * the call only.  Errors: SN_EINVAL (null arrays with nnz > 0, non-finite w),
+ * SN_ERANGE (index or delay out of range), SN_ENOMEM, SN_EDEVICE. */
+sn_status sn_load_weights_delays(sn_net* net, int64_t nnz, const int32_t* pre, const int32_t* post,
+                                 const float* w, const uint8_t* delay);
+
+/* Loads a dense N x N weight matrix (host, row-major, row = pre-neuron,
+ * column = post-neuron, §2.1) whose synapses all have delay `delay`; zero
+ * entries are absent synapses.  This build supports delay == 1.  Weights are
+ * held as bfloat16 for the matrix cores, so every entry must be exactly
+ * representable in bfloat16 (SN_EINEXACT otherwise).  Enables SN_PATH_DENSE
+ * and also loads the nonzeros as a sparse list for the other paths.
+ * Errors: SN_EINVAL, SN_ERANGE (delay), SN_EINEXACT, SN_ENOMEM, SN_EDEVICE. */
+sn_status sn_load_dense_weights(sn_net* net, const float* W, int32_t delay);
+
+/* External spikes (§2.1, third step) for steps t0 .. t0+n_steps-1.  `bits`
+ * is host memory laid out [B][n_steps][ceil(N/32)] uint32 words; bit (j % 32)
+ * of word j / 32 is neuron j.  Bits of neurons >= N are ignored.  Steps never
+ * given have no external spikes.  Steps already simulated may be rewritten;
+ * that affects only a later sn_reset_state + sn_run.  Errors: SN_EINVAL,
+ * SN_ERANGE (t0 < 0 or n_steps < 0), SN_ENOMEM, SN_EDEVICE. */
+sn_status sn_set_input_spikes(sn_net* net, int32_t t0, int32_t n_steps, const uint32_t* bits);
+
+/* Same, with `bits` in device memory (same layout), copied on the stream. */
+sn_status sn_set_input_spikes_device(sn_net* net, int32_t t0, int32_t n_steps, const uint32_t* bits);
+
+/* Advances the simulation by n_steps steps (t -> t + n_steps), asynchronously
+ * on the network's stream.  Resumable: run(a) followed by run(b) equals
+ * run(a + b).  Requires synapses (sn_load_* may have loaded zero synapses).
+ * Errors: SN_ESTATE (no synapses loaded, or poisoned), SN_ERANGE, SN_ENOMEM,
+ * SN_EDEVICE. */
+sn_status sn_run(sn_net* net, int32_t n_steps);
+
+/* Blocks until all device work of the network has finished. */
+sn_status sn_synchronize(sn_net* net);
+
+/* Copies the spikes of steps t0 .. t0+n_steps-1 to host memory `out`, laid
+ * out like sn_set_input_spikes ([B][n_steps][ceil(N/32)] words).  Waits for
+ * the work in flight.  Errors: SN_EINVAL, SN_ERANGE (steps not simulated). */
+sn_status sn_read_raster(sn_net* net, int32_t t0, int32_t n_steps, uint32_t* out);
+
+/* Copies the state after the last simulated step: V [B][N] floats and the
+ * remaining refractory steps [B][N] (either pointer may be NULL).  Waits for
+ * the work in flight. */
+sn_status sn_read_state(sn_net* net, float* V, uint8_t* refractory_left);
+
+/* Returns to the initial state (t = 0, V = r, counters 0, history cleared);
+ * synapses and external spikes are kept.  Asynchronous on the stream. */
+sn_status sn_reset_state(sn_net* net);
+
+/* Selects the execution strategy (SN_PATH_*); checked at the next sn_run. */
+sn_status sn_set_path(sn_net* net, int32_t path);
+
+/* Number of slices (workgroups per trial) of SN_PATH_PERSIST: 0 picks the
+ * fewest slices whose synapse records fit in on-chip memory (or one per
+ * compute unit when they cannot); 1..256 forces a count (clamped to the
+ * number of 64-neuron groups).  A tuning knob: results do not change.
+ * Errors: SN_ERANGE. */
+sn_status sn_set_slices(sn_net* net, int32_t slices);
+
+/* Reports the number of simulated steps so far (*t) and the strategy the
+ * last sn_run used (*path, SN_PATH_AUTO before the first run). */
+sn_status sn_get_progress(sn_net* net, int32_t* t, int32_t* path);
+
+/* Frees the network and its device memory after its work has finished.
+ * NULL is ignored. */
+void sn_destroy_network(sn_net* net);
+
+/* Message of the calling thread's most recent failure ("" if none). */
+const char* sn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUPERNEURO_MI_H */

@@ -1,0 +1,590 @@
+// C ABI (include/superneuro_mi.h): validation, device memory, layout upload,
+// path selection and launches.  Host-only code; kernels live in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/superneuro_mi.h"
+#include "sn_internal.h"
+
+using namespace snmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+sn_status fail(sn_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace
+
+struct sn_net {
+  DevNet d{};
+  hipStream_t stream = nullptr;
+  sn_allocator alloc{};
+  bool custom_alloc = false;
+  int device = 0;
+  std::vector<float> h_reset;
+  // owned device buffers
+  std::vector<void*> owned;
+  int64_t tcap = 0;  // rows allocated in raster and ext
+  int32_t t = 0;     // steps simulated
+  bool synapses_loaded = false;
+  bool poisoned = false;
+  int32_t path = SN_PATH_AUTO;
+  int32_t last_path = SN_PATH_AUTO;
+  // synapse buffers (replaced by a new load)
+  void* recs = nullptr;
+  void* gptr = nullptr;
+  void* chunks = nullptr;
+  // persistent-kernel plans: one slice (SMALL) and several slices (PERSIST)
+  struct DevPlan {
+    SlicePlan host;
+    void* wg = nullptr;  // [2][P + 1] int32: wg_group then wg_chunk
+    bool ok = false;
+  };
+  DevPlan small, persist;
+  int32_t slices_req = 0;
+  uint32_t* flags = nullptr;  // [B][256]
+  uint32_t* status = nullptr;
+  HostLayout layout;          // kept to re-plan when the slice count changes
+};
+
+namespace {
+
+void* dev_alloc(sn_net* n, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (n->custom_alloc) {
+    p = n->alloc.alloc(bytes, n->alloc.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  return p;
+}
+
+void dev_free(sn_net* n, void* p) {
+  if (!p) return;
+  if (n->custom_alloc) {
+    n->alloc.free(p, n->alloc.ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+sn_status device_error(sn_net* n, hipError_t e, const char* what) {
+  n->poisoned = true;
+  return fail(SN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SN_HIP(net, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return device_error(net, e_, #call); \
+  } while (0)
+
+sn_status check_usable(sn_net* n) {
+  if (!n) return fail(SN_EINVAL, "network is NULL");
+  if (n->poisoned) return fail(SN_ESTATE, "network is poisoned by an earlier device error");
+  return SN_OK;
+}
+
+// Grows raster and ext to hold at least `rows` steps (doubling), preserving
+// the simulated rows of the raster and all rows of ext.
+sn_status ensure_rows(sn_net* n, int64_t rows) {
+  if (rows <= n->tcap) return SN_OK;
+  int64_t cap = std::max<int64_t>(rows, std::max<int64_t>(64, n->tcap * 2));
+  const size_t row_bytes = static_cast<size_t>(n->d.B) * n->d.G * sizeof(uint64_t);
+  void* nr = dev_alloc(n, cap * row_bytes);
+  void* ne = dev_alloc(n, cap * row_bytes);
+  if (!nr || !ne) {
+    dev_free(n, nr);
+    dev_free(n, ne);
+    return fail(SN_ENOMEM, "cannot allocate %lld spike rows", static_cast<long long>(cap));
+  }
+  SN_HIP(n, hipMemsetAsync(nr, 0, cap * row_bytes, n->stream));
+  SN_HIP(n, hipMemsetAsync(ne, 0, cap * row_bytes, n->stream));
+  if (n->tcap > 0) {
+    SN_HIP(n, hipMemcpyAsync(nr, n->d.raster, n->tcap * row_bytes, hipMemcpyDeviceToDevice, n->stream));
+    SN_HIP(n, hipMemcpyAsync(ne, n->d.ext, n->tcap * row_bytes, hipMemcpyDeviceToDevice, n->stream));
+  }
+  // old buffers may still be read by queued kernels: free after the stream drains
+  if (n->tcap > 0) {
+    SN_HIP(n, hipStreamSynchronize(n->stream));
+    dev_free(n, n->d.raster);
+    dev_free(n, const_cast<uint64_t*>(n->d.ext));
+  }
+  n->d.raster = static_cast<uint64_t*>(nr);
+  n->d.ext = static_cast<const uint64_t*>(ne);
+  n->tcap = cap;
+  return SN_OK;
+}
+
+// Chooses where the persistent kernel keeps records and the spike ring;
+// false if the slice plan cannot run at all.
+bool fit_plan(const DevNet& d, SlicePlan& p) {
+  if (p.P < 1 || sim_npt(p.ng_max) > 8) return false;
+  const bool opts[4][2] = {{true, true}, {true, false}, {false, true}, {false, false}};
+  for (const auto& o : opts) {
+    if (sim_lds_bytes(d, p.ng_max, p.max_recs, o[0], o[1]) <= lds_limit()) {
+      p.recs_lds = o[0];
+      p.ring_lds = o[1];
+      return true;
+    }
+  }
+  return false;
+}
+
+constexpr int32_t kMaxCoopGroups = 256;  // one workgroup per CU of an MI355X
+
+// Slice plan for the multi-workgroup persistent kernel: the fewest slices
+// whose records fit in LDS (fewest barrier participants), else one slice per
+// CU streaming records from global memory.
+SlicePlan plan_persist(const DevNet& d, const HostLayout& L, int32_t slices_req) {
+  const int32_t pmax = std::max(1, kMaxCoopGroups / d.B);
+  const int32_t top = std::min(d.G, pmax);
+  if (slices_req > 0) {
+    SlicePlan p = partition_groups(L, d.G, std::min(slices_req, top), 128);
+    if (!fit_plan(d, p)) p.P = 0;
+    return p;
+  }
+  int32_t lo = 1, hi = top;
+  auto resident = [&](int32_t P, SlicePlan* out) {
+    SlicePlan p = partition_groups(L, d.G, P, 128);
+    const bool ok = fit_plan(d, p) && p.recs_lds;
+    if (out) *out = p;
+    return ok;
+  };
+  if (resident(hi, nullptr)) {
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      if (resident(mid, nullptr)) hi = mid; else lo = mid + 1;
+    }
+    SlicePlan p;
+    resident(lo, &p);
+    return p;
+  }
+  SlicePlan p = partition_groups(L, d.G, top, 128);
+  if (!fit_plan(d, p)) p.P = 0;
+  return p;
+}
+
+sn_status upload_plan(sn_net* n, sn_net::DevPlan& dp, const SlicePlan& p) {
+  dev_free(n, dp.wg);
+  dp.wg = nullptr;
+  dp.host = p;
+  dp.ok = p.P > 0;
+  if (!dp.ok) return SN_OK;
+  std::vector<int32_t> buf(p.wg_group);
+  buf.insert(buf.end(), p.wg_chunk.begin(), p.wg_chunk.end());
+  dp.wg = dev_alloc(n, buf.size() * sizeof(int32_t));
+  if (!dp.wg) return fail(SN_ENOMEM, "cannot allocate slice tables");
+  SN_HIP(n, hipMemcpyAsync(dp.wg, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  return SN_OK;
+}
+
+SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
+  SimArgs a{};
+  a.n = n->d;
+  a.wg_group = static_cast<const int32_t*>(dp.wg);
+  a.wg_chunk = static_cast<const int32_t*>(dp.wg) + dp.host.P + 1;
+  a.flags = n->flags;
+  a.status = n->status;
+  a.P = dp.host.P;
+  a.ng_max = dp.host.ng_max;
+  a.max_recs = dp.host.max_recs;
+  return a;
+}
+
+// Reads the barrier-timeout flag of the persistent kernel (after a sync).
+sn_status check_status(sn_net* n) {
+  uint32_t st = 0;
+  SN_HIP(n, hipMemcpy(&st, n->status, sizeof(st), hipMemcpyDeviceToHost));
+  if (st != 0) {
+    n->poisoned = true;
+    return fail(SN_EDEVICE, "a grid-barrier wait of the persistent kernel timed out");
+  }
+  return SN_OK;
+}
+
+bool on_device_ok(sn_net* n) {
+  int cur = -1;
+  return hipGetDevice(&cur) == hipSuccess && cur == n->device;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sn_last_error(void) { return g_err.c_str(); }
+
+sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc, void* hip_stream, sn_net** out) {
+  if (!desc || !out) return fail(SN_EINVAL, "desc and out must not be NULL");
+  *out = nullptr;
+  const int32_t N = desc->n_neurons, B = desc->n_trials, D = desc->max_delay;
+  if (N < 1 || N > SN_MAX_NEURONS) return fail(SN_ERANGE, "n_neurons %d outside [1, %d]", N, SN_MAX_NEURONS);
+  if (B < 1 || B > 65535) return fail(SN_ERANGE, "n_trials %d outside [1, 65535]", B);
+  if (D < 1 || D > SN_MAX_DELAY) return fail(SN_ERANGE, "max_delay %d outside [1, %d]", D, SN_MAX_DELAY);
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(SN_EINVAL, "allocator needs alloc and free");
+
+  const int32_t G = (N + kGroup - 1) / kGroup, Npad = G * kGroup;
+  std::vector<float> th(Npad, INFINITY), lk(Npad, 0.f), rs(Npad, 0.f), am(Npad, 0.f);
+  std::vector<uint8_t> rf(Npad, 0);
+  for (int32_t j = 0; j < N; ++j) {
+    th[j] = desc->threshold ? desc->threshold[j] : desc->threshold_scalar;
+    lk[j] = desc->leak ? desc->leak[j] : desc->leak_scalar;
+    rs[j] = desc->reset ? desc->reset[j] : desc->reset_scalar;
+    am[j] = desc->amplitude ? desc->amplitude[j] : desc->amplitude_scalar;
+    rf[j] = desc->refractory ? desc->refractory[j] : desc->refractory_scalar;
+    if (!std::isfinite(th[j])) return fail(SN_EINVAL, "threshold of neuron %d is not finite", j);
+    if (!std::isfinite(rs[j])) return fail(SN_EINVAL, "reset of neuron %d is not finite", j);
+    if (!std::isfinite(am[j])) return fail(SN_EINVAL, "amplitude of neuron %d is not finite", j);
+    if (!(lk[j] >= 0.f)) return fail(SN_EINVAL, "leak of neuron %d must be >= 0 (got %g)", j, lk[j]);
+  }
+
+  sn_net* n = new (std::nothrow) sn_net();
+  if (!n) return fail(SN_ENOMEM, "out of host memory");
+  if (hipGetDevice(&n->device) != hipSuccess) {
+    delete n;
+    (void)hipGetLastError();
+    return fail(SN_EDEVICE, "no HIP device available");
+  }
+  n->stream = static_cast<hipStream_t>(hip_stream);
+  if (alloc) {
+    n->alloc = *alloc;
+    n->custom_alloc = true;
+  }
+  n->d.N = N;
+  n->d.Npad = Npad;
+  n->d.G = G;
+  n->d.B = B;
+  n->d.D = D;
+  n->h_reset = rs;
+
+  auto upload = [&](const void* src, size_t bytes) -> void* {
+    void* p = dev_alloc(n, bytes);
+    if (!p) return nullptr;
+    n->owned.push_back(p);
+    if (hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, n->stream) != hipSuccess) return nullptr;
+    return p;
+  };
+  n->d.theta = static_cast<const float*>(upload(th.data(), Npad * sizeof(float)));
+  n->d.leak = static_cast<const float*>(upload(lk.data(), Npad * sizeof(float)));
+  n->d.reset = static_cast<const float*>(upload(rs.data(), Npad * sizeof(float)));
+  n->d.amp = static_cast<const float*>(upload(am.data(), Npad * sizeof(float)));
+  n->d.refr = static_cast<const uint8_t*>(upload(rf.data(), Npad));
+  void* V = dev_alloc(n, static_cast<size_t>(B) * Npad * sizeof(float));
+  if (V) n->owned.push_back(V);
+  void* R = dev_alloc(n, static_cast<size_t>(B) * Npad);
+  if (R) n->owned.push_back(R);
+  n->d.V = static_cast<float*>(V);
+  n->d.ref = static_cast<uint8_t*>(R);
+  void* F = dev_alloc(n, static_cast<size_t>(B) * kMaxCoopGroups * sizeof(uint32_t) + 256);
+  if (F) n->owned.push_back(F);
+  n->flags = static_cast<uint32_t*>(F);
+  n->status = F ? reinterpret_cast<uint32_t*>(static_cast<char*>(F) + static_cast<size_t>(B) * kMaxCoopGroups * 4) : nullptr;
+  if (F && hipMemsetAsync(F, 0, static_cast<size_t>(B) * kMaxCoopGroups * sizeof(uint32_t) + 256, n->stream) != hipSuccess) F = nullptr;
+  if (!n->d.theta || !n->d.leak || !n->d.reset || !n->d.amp || !n->d.refr || !V || !R || !F) {
+    sn_destroy_network(n);
+    return fail(SN_ENOMEM, "cannot allocate or upload neuron arrays");
+  }
+  if (launch_reset_state(n->d, n->stream) != hipSuccess) {
+    sn_destroy_network(n);
+    return fail(SN_EDEVICE, "state initialisation failed");
+  }
+  sn_status st = ensure_rows(n, 64);
+  if (st != SN_OK) {
+    sn_destroy_network(n);
+    return st;
+  }
+  if (hipStreamSynchronize(n->stream) != hipSuccess) {
+    sn_destroy_network(n);
+    return fail(SN_EDEVICE, "stream synchronisation failed");
+  }
+  *out = n;
+  return SN_OK;
+}
+
+sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
+                                 const uint8_t* delay) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (nnz < 0) return fail(SN_EINVAL, "nnz must be >= 0");
+  if (nnz > 0 && (!pre || !post || !w || !delay)) return fail(SN_EINVAL, "synapse arrays must not be NULL");
+  if (nnz >= (int64_t(1) << 31)) return fail(SN_ERANGE, "at most 2^31 - 1 synapses");
+  for (int64_t k = 0; k < nnz; ++k) {
+    if (pre[k] < 0 || pre[k] >= n->d.N) return fail(SN_ERANGE, "synapse %lld: pre %d outside [0, %d)", (long long)k, pre[k], n->d.N);
+    if (post[k] < 0 || post[k] >= n->d.N) return fail(SN_ERANGE, "synapse %lld: post %d outside [0, %d)", (long long)k, post[k], n->d.N);
+    if (delay[k] < 1 || delay[k] > n->d.D) return fail(SN_ERANGE, "synapse %lld: delay %d outside [1, %d]", (long long)k, delay[k], n->d.D);
+    if (!std::isfinite(w[k])) return fail(SN_EINVAL, "synapse %lld: weight is not finite", (long long)k);
+  }
+  if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
+  HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay);
+  void* recs = dev_alloc(n, L.recs.size() * sizeof(Rec));
+  void* gptr = dev_alloc(n, L.gptr.size() * sizeof(int32_t));
+  void* chunks = dev_alloc(n, L.chunks.size() * sizeof(uint2));
+  if (!recs || !gptr || !chunks) {
+    dev_free(n, recs);
+    dev_free(n, gptr);
+    dev_free(n, chunks);
+    return fail(SN_ENOMEM, "cannot allocate synapse records");
+  }
+  // the previous buffers may be in use by queued work
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  dev_free(n, n->recs);
+  dev_free(n, n->gptr);
+  dev_free(n, n->chunks);
+  n->recs = recs;
+  n->gptr = gptr;
+  n->chunks = chunks;
+  if (!L.recs.empty())
+    SN_HIP(n, hipMemcpyAsync(recs, L.recs.data(), L.recs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
+  SN_HIP(n, hipMemcpyAsync(gptr, L.gptr.data(), L.gptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+  if (!L.chunks.empty())
+    SN_HIP(n, hipMemcpyAsync(chunks, L.chunks.data(), L.chunks.size() * sizeof(uint2), hipMemcpyHostToDevice, n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));  // host vectors die at return
+  n->d.recs = static_cast<const Rec*>(recs);
+  n->d.gptr = static_cast<const int32_t*>(gptr);
+  n->d.chunks = static_cast<const uint2*>(chunks);
+  n->d.nnz = nnz;
+  n->d.nchunks = static_cast<int32_t>(L.chunks.size());
+  n->synapses_loaded = true;
+  SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
+  if (!fit_plan(n->d, one)) one.P = 0;
+  st = upload_plan(n, n->small, one);
+  if (st != SN_OK) return st;
+  st = upload_plan(n, n->persist, plan_persist(n->d, L, n->slices_req));
+  if (st != SN_OK) return st;
+  n->layout = std::move(L);
+  return SN_OK;
+}
+
+sn_status sn_set_slices(sn_net* n, int32_t slices) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (slices < 0 || slices > kMaxCoopGroups) return fail(SN_ERANGE, "slices %d outside [0, %d]", slices, kMaxCoopGroups);
+  n->slices_req = slices;
+  if (n->synapses_loaded) return upload_plan(n, n->persist, plan_persist(n->d, n->layout, slices));
+  return SN_OK;
+}
+
+sn_status sn_load_dense_weights(sn_net* n, const float* W, int32_t delay) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (!W) return fail(SN_EINVAL, "W must not be NULL");
+  if (delay != 1) return fail(SN_ERANGE, "dense weights support delay 1 only (got %d)", delay);
+  const int32_t N = n->d.N;
+  std::vector<int32_t> pre, post;
+  std::vector<float> w;
+  for (int32_t i = 0; i < N; ++i) {
+    for (int32_t j = 0; j < N; ++j) {
+      const float x = W[static_cast<size_t>(i) * N + j];
+      if (!std::isfinite(x)) return fail(SN_EINVAL, "W[%d][%d] is not finite", i, j);
+      uint32_t u;
+      std::memcpy(&u, &x, 4);
+      if ((u & 0xFFFFu) != 0u) return fail(SN_EINEXACT, "W[%d][%d] = %g is not exact in bfloat16", i, j, x);
+      if (x != 0.f) {
+        pre.push_back(i);
+        post.push_back(j);
+        w.push_back(x);
+      }
+    }
+  }
+  std::vector<uint8_t> d(w.size(), 1);
+  return sn_load_weights_delays(n, static_cast<int64_t>(w.size()), pre.data(), post.data(), w.data(), d.data());
+}
+
+sn_status sn_set_input_spikes(sn_net* n, int32_t t0, int32_t n_steps, const uint32_t* bits) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (t0 < 0 || n_steps < 0) return fail(SN_ERANGE, "t0 and n_steps must be >= 0");
+  if (n_steps > 0 && !bits) return fail(SN_EINVAL, "bits must not be NULL");
+  if (n_steps == 0) return SN_OK;
+  if (static_cast<int64_t>(t0) + n_steps > INT32_MAX) return fail(SN_ERANGE, "step range overflows");
+  st = ensure_rows(n, static_cast<int64_t>(t0) + n_steps);
+  if (st != SN_OK) return st;
+  const int32_t B = n->d.B, G = n->d.G, N = n->d.N, W32 = (N + 31) / 32;
+  std::vector<uint64_t> rows(static_cast<size_t>(n_steps) * B * G);
+  for (int32_t b = 0; b < B; ++b) {
+    for (int32_t i = 0; i < n_steps; ++i) {
+      const uint32_t* src = bits + (static_cast<size_t>(b) * n_steps + i) * W32;
+      uint64_t* dst = rows.data() + (static_cast<size_t>(i) * B + b) * G;
+      for (int32_t g = 0; g < G; ++g) {
+        const uint32_t lo = src[2 * g];
+        const uint32_t hi = (2 * g + 1 < W32) ? src[2 * g + 1] : 0u;
+        uint64_t v = (static_cast<uint64_t>(hi) << 32) | lo;
+        const int valid = N - g * kGroup;
+        if (valid < 64) v &= (1ull << valid) - 1ull;
+        dst[g] = v;
+      }
+    }
+  }
+  const size_t row_bytes = static_cast<size_t>(B) * G * sizeof(uint64_t);
+  SN_HIP(n, hipMemcpyAsync(const_cast<uint64_t*>(n->d.ext) + static_cast<size_t>(t0) * B * G, rows.data(),
+                           rows.size() * sizeof(uint64_t), hipMemcpyHostToDevice, n->stream));
+  (void)row_bytes;
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  return SN_OK;
+}
+
+sn_status sn_set_input_spikes_device(sn_net* n, int32_t t0, int32_t n_steps, const uint32_t* bits) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (t0 < 0 || n_steps < 0) return fail(SN_ERANGE, "t0 and n_steps must be >= 0");
+  if (n_steps > 0 && !bits) return fail(SN_EINVAL, "bits must not be NULL");
+  if (n_steps == 0) return SN_OK;
+  if (static_cast<int64_t>(t0) + n_steps > INT32_MAX) return fail(SN_ERANGE, "step range overflows");
+  st = ensure_rows(n, static_cast<int64_t>(t0) + n_steps);
+  if (st != SN_OK) return st;
+  SN_HIP(n, launch_repack_input(n->d, t0, n_steps, bits, n->stream));
+  return SN_OK;
+}
+
+sn_status sn_set_path(sn_net* n, int32_t path) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (path < SN_PATH_AUTO || path > SN_PATH_DENSE) return fail(SN_ERANGE, "unknown path %d", path);
+  n->path = path;
+  return SN_OK;
+}
+
+sn_status sn_get_progress(sn_net* n, int32_t* t, int32_t* path) {
+  if (!n) return fail(SN_EINVAL, "network is NULL");
+  if (t) *t = n->t;
+  if (path) *path = n->last_path;
+  return SN_OK;
+}
+
+sn_status sn_run(sn_net* n, int32_t n_steps) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_run");
+  if (n_steps < 0) return fail(SN_ERANGE, "n_steps must be >= 0");
+  if (static_cast<int64_t>(n->t) + n_steps > INT32_MAX) return fail(SN_ERANGE, "step counter overflows");
+  if (n_steps == 0) return SN_OK;
+  if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
+  st = ensure_rows(n, static_cast<int64_t>(n->t) + n_steps);
+  if (st != SN_OK) return st;
+
+  int32_t path = n->path;
+  if (path == SN_PATH_AUTO) {
+    // one workgroup when its records and spike ring fit in LDS, otherwise one
+    // launch per step
+    path = (n->small.ok && n->small.host.recs_lds && n->small.host.ring_lds) ? SN_PATH_SMALL : SN_PATH_STEP;
+  }
+  switch (path) {
+    case SN_PATH_SMALL:
+      if (!n->small.ok) return fail(SN_ERANGE, "network too large for the single-workgroup path");
+      SN_HIP(n, launch_sim(sim_args(n, n->small), n->small.host.recs_lds, n->small.host.ring_lds, n->t, n_steps,
+                           n->stream));
+      break;
+    case SN_PATH_PERSIST: {
+      if (!n->persist.ok) return fail(SN_ERANGE, "no slice plan fits the persistent kernel");
+      SimArgs a = sim_args(n, n->persist);
+      SN_HIP(n, launch_clear_u32(n->flags, n->d.B * a.P, n->stream));
+      SN_HIP(n, launch_sim(a, n->persist.host.recs_lds, n->persist.host.ring_lds, n->t, n_steps, n->stream));
+      break;
+    }
+    case SN_PATH_STEP:
+      for (int32_t k = 0; k < n_steps; ++k) SN_HIP(n, launch_step(n->d, n->t + k, n->stream));
+      break;
+    default:
+      return fail(SN_ERANGE, "path %d is not available in this build", path);
+  }
+  n->t += n_steps;
+  n->last_path = path;
+  return SN_OK;
+}
+
+sn_status sn_synchronize(sn_net* n) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  return check_status(n);
+}
+
+sn_status sn_read_raster(sn_net* n, int32_t t0, int32_t n_steps, uint32_t* out) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (n_steps > 0 && !out) return fail(SN_EINVAL, "out must not be NULL");
+  if (t0 < 0 || n_steps < 0 || static_cast<int64_t>(t0) + n_steps > n->t)
+    return fail(SN_ERANGE, "steps [%d, %lld) not simulated (t = %d)", t0, (long long)t0 + n_steps, n->t);
+  if (n_steps == 0) return SN_OK;
+  const int32_t B = n->d.B, G = n->d.G, N = n->d.N, W32 = (N + 31) / 32;
+  std::vector<uint64_t> rows(static_cast<size_t>(n_steps) * B * G);
+  SN_HIP(n, hipMemcpyAsync(rows.data(), n->d.raster + static_cast<size_t>(t0) * B * G, rows.size() * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  st = check_status(n);
+  if (st != SN_OK) return st;
+  for (int32_t b = 0; b < B; ++b) {
+    for (int32_t i = 0; i < n_steps; ++i) {
+      const uint64_t* src = rows.data() + (static_cast<size_t>(i) * B + b) * G;
+      uint32_t* dst = out + (static_cast<size_t>(b) * n_steps + i) * W32;
+      for (int32_t g = 0; g < G; ++g) {
+        dst[2 * g] = static_cast<uint32_t>(src[g]);
+        if (2 * g + 1 < W32) dst[2 * g + 1] = static_cast<uint32_t>(src[g] >> 32);
+      }
+    }
+  }
+  return SN_OK;
+}
+
+sn_status sn_read_state(sn_net* n, float* V, uint8_t* refractory_left) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  const int32_t B = n->d.B, N = n->d.N, Npad = n->d.Npad;
+  std::vector<float> hv(static_cast<size_t>(B) * Npad);
+  std::vector<uint8_t> hr(static_cast<size_t>(B) * Npad);
+  SN_HIP(n, hipMemcpyAsync(hv.data(), n->d.V, hv.size() * sizeof(float), hipMemcpyDeviceToHost, n->stream));
+  SN_HIP(n, hipMemcpyAsync(hr.data(), n->d.ref, hr.size(), hipMemcpyDeviceToHost, n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  st = check_status(n);
+  if (st != SN_OK) return st;
+  for (int32_t b = 0; b < B; ++b) {
+    if (V) std::memcpy(V + static_cast<size_t>(b) * N, hv.data() + static_cast<size_t>(b) * Npad, N * sizeof(float));
+    if (refractory_left)
+      std::memcpy(refractory_left + static_cast<size_t>(b) * N, hr.data() + static_cast<size_t>(b) * Npad, N);
+  }
+  return SN_OK;
+}
+
+sn_status sn_reset_state(sn_net* n) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  SN_HIP(n, launch_reset_state(n->d, n->stream));
+  n->t = 0;
+  return SN_OK;
+}
+
+void sn_destroy_network(sn_net* n) {
+  if (!n) return;
+  (void)hipStreamSynchronize(n->stream);
+  for (void* p : n->owned) dev_free(n, p);
+  dev_free(n, n->d.raster);
+  dev_free(n, const_cast<uint64_t*>(n->d.ext));
+  dev_free(n, n->recs);
+  dev_free(n, n->gptr);
+  dev_free(n, n->chunks);
+  dev_free(n, n->small.wg);
+  dev_free(n, n->persist.wg);
+  delete n;
+}
+
+}  // extern "C"

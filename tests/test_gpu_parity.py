@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Inputs are dyadic, so every sum is exact in binary32 and the oracle's double
+results are the unique answer: rasters must match exactly, membrane states at
+0 ULP and refractory counters exactly.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+from paper_2305_02510_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_02510_amd import Network
+    return Network
+
+
+def simulate(Network, net, path="auto", chunks=None, slices=0):
+    g = Network.from_workload(net)
+    g.set_path(path)
+    if slices:
+        g.set_slices(slices)
+    for c in (chunks or [net.steps]):
+        g.run(c)
+    spikes = g.read_raster(0, net.steps)
+    V, ref = g.read_state()
+    used = g.progress[1]
+    g.close()
+    return spikes, V, ref, used
+
+
+def assert_parity(net, res, spikes, V, ref, what=""):
+    assert res.exact, f"{net.name}: input violates the exactness premise"
+    if not np.array_equal(spikes, res.spikes):
+        b, t, j = np.argwhere(spikes != res.spikes)[0]
+        raise AssertionError(f"{net.name} {what}: raster differs first at trial {b} step {t} neuron {j} "
+                             f"(gpu {spikes[b, t, j]}, oracle {res.spikes[b, t, j]}); "
+                             f"{int((spikes != res.spikes).sum())} bits differ")
+    assert np.array_equal(V.astype(np.float64), res.V), f"{net.name} {what}: V differs"
+    assert np.array_equal(ref.astype(np.int32), res.ref), f"{net.name} {what}: refractory counters differ"
+
+
+PATHS = ["small", "step", "persist"]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_single_lif(gpu, oracle, path):
+    net = wl.single_lif(1)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, path)
+    assert used == path
+    assert_parity(net, res, s, V, r, path)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("path", PATHS)
+def test_random_small(gpu, oracle, seed, path):
+    net = wl.random_small(1000 + seed, n=[5, 64, 65, 130, 17, 200][seed], p=0.25,
+                          max_delay=[1, 4, 8, 16, 64, 3][seed], steps=120, trials=1 + seed % 3, hetero=True)
+    res = oracle.run_sparse(net)
+    s, V, r, _ = simulate(gpu, net, path)
+    assert_parity(net, res, s, V, r, path)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_resumable(gpu, oracle, path):
+    net = wl.random_small(77, n=90, p=0.2, max_delay=6, steps=100, trials=2, hetero=True)
+    res = oracle.run_sparse(net)
+    for chunks in ([1] * 7 + [93], [33, 0, 67], [5, 50, 45]):
+        s, V, r, _ = simulate(gpu, net, path, chunks)
+        assert_parity(net, res, s, V, r, f"{path} chunks {chunks}")
+
+
+def test_mixed_paths_and_reset(gpu, oracle):
+    net = wl.random_small(78, n=70, p=0.3, max_delay=5, steps=80, hetero=True)
+    res = oracle.run_sparse(net)
+    g = gpu.from_workload(net)
+    for path, c in [("small", 13), ("step", 20), ("persist", 9), ("small", 31), ("step", 7)]:
+        g.set_path(path)
+        g.run(c)
+    assert_parity(net, res, g.read_raster(0, 80), *g.read_state(), "mixed")
+    g.reset_state()
+    g.set_path("step")
+    g.run(80)
+    assert_parity(net, res, g.read_raster(0, 80), *g.read_state(), "after reset")
+    g.close()
+
+
+def test_large_sparse_full(gpu, oracle):
+    """N = 10,000, ~1M synapses, delays 1..16, T = 1000: the benchmarked net,
+    in the launch configuration the benchmark uses (auto) and per-step."""
+    net = wl.large_sparse(2)
+    res = oracle.run_sparse(net)
+    for path in ("auto", "step"):
+        s, V, r, used = simulate(gpu, net, path)
+        assert_parity(net, res, s, V, r, used)
+
+
+@pytest.mark.parametrize("slices", [1, 2, 7, 40, 256])
+def test_persist_slices(gpu, oracle, slices):
+    """Forced slice counts: one slice (no barrier), few slices (records
+    streamed from global memory), many slices."""
+    net = wl.large_sparse(12, n=3000, p=0.02, steps=150)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "persist", chunks=[60, 90], slices=slices)
+    assert used == "persist"
+    assert_parity(net, res, s, V, r, f"slices={slices}")
+
+
+def test_persist_global_ring(gpu, oracle):
+    """A spike ring too large for LDS (N = 40,000, D = 64): bits come from the
+    raster in global memory."""
+    net = wl.large_sparse(13, n=40_000, p=0.0005, steps=120, max_delay=64)
+    res = oracle.run_sparse(net)
+    for path in ("persist", "step"):
+        s, V, r, used = simulate(gpu, net, path)
+        assert_parity(net, res, s, V, r, path)
+
+
+def test_large_sparse_low_rate(gpu, oracle):
+    net = wl.large_sparse_low(2, steps=300)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "auto")
+    assert_parity(net, res, s, V, r, used)
+
+
+@pytest.mark.parametrize("n,p", [(100, 0.25), (100, 1.0), (1000, 0.25)])
+def test_paper_table_shapes(gpu, oracle, n, p):
+    net = wl.paper_table_shape(5, n, p)
+    res = oracle.run_sparse(net)
+    for path in PATHS:
+        try:
+            s, V, r, _ = simulate(gpu, net, path)
+        except Exception as e:  # the single-workgroup path refuses nets that do not fit
+            assert path == "small" and "SN_ERANGE" in str(e)
+            continue
+        assert_parity(net, res, s, V, r, path)
+
+
+def test_edge_cases(gpu, oracle):
+    from oracle_pins import tiny_net
+    cases = [
+        tiny_net(1, steps=20, ext_events=[(0, t, 0) for t in range(0, 20, 3)], refractory=255),
+        tiny_net(3, steps=10),                                      # no synapses, no input
+        tiny_net(2, [0, 0, 0], [1, 1, 1], [0.5, 0.25, 0.375], [2, 2, 2], steps=12,
+                 ext_events=[(0, 1, 0)]),                           # duplicate synapses sum to 1.125
+        tiny_net(2, [0, 1], [0, 1], [1.5, 1.5], [1, 64], steps=200,
+                 ext_events=[(0, 0, 0), (0, 0, 1)], refractory=0),  # self-loops, maximum delay
+    ]
+    # relay neurons with infinite leak, as in the paper's proxy construction
+    inf_net = tiny_net(3, [0, 1], [1, 2], [1.0, 1.5], [1, 1], steps=10, ext_events=[(0, 2, 0)])
+    inf_net.threshold[1] = 0.0
+    inf_net.leak[1] = np.inf
+    cases.append(inf_net)
+    for net in cases:
+        res = oracle.run_sparse(net)
+        for path in PATHS:
+            s, V, r, _ = simulate(gpu, net, path)
+            assert_parity(net, res, s, V, r, path)
+
+
+def test_device_input(gpu, oracle):
+    import torch
+    from paper_2305_02510_amd.network import pack_bits
+    net = wl.random_small(90, n=100, p=0.2, max_delay=4, steps=60, trials=2)
+    res = oracle.run_sparse(net)
+    g = gpu(net.n, net.trials, net.max_delay, net.threshold, net.leak, net.reset, net.refractory, net.amplitude)
+    g.load_weights_delays(net.pre, net.post, net.weight, net.delay)
+    words = torch.from_numpy(pack_bits(net.ext).view(np.int32)).cuda()
+    g.set_input_spikes_device(0, words)
+    g.run(net.steps)
+    assert_parity(net, res, g.read_raster(0, net.steps), *g.read_state(), "device input")
+    g.close()
+
+
+def test_error_paths(gpu):
+    from paper_2305_02510_amd._lib import SnError
+    g = gpu(10, 1, 2)
+    with pytest.raises(SnError, match="SN_ESTATE"):
+        g.run(5)                                     # no synapses yet
+    with pytest.raises(SnError, match="SN_ERANGE"):
+        g.load_weights_delays([0], [10], [1.0], [1])  # post out of range
+    with pytest.raises(SnError, match="SN_ERANGE"):
+        g.load_weights_delays([0], [1], [1.0], [3])   # delay above max_delay
+    with pytest.raises(SnError, match="SN_EINVAL"):
+        g.load_weights_delays([0], [1], [np.nan], [1])
+    g.load_weights_delays([0], [1], [1.5], [2])
+    g.run(4)
+    with pytest.raises(SnError, match="SN_ERANGE"):
+        g.read_raster(0, 5)                          # only 4 steps simulated
+    assert g.progress[0] == 4
+    with pytest.raises(SnError, match="SN_EINEXACT"):
+        W = np.zeros((10, 10), np.float32)
+        W[0, 1] = 1.0 + 2.0 ** -10                   # not a bfloat16 value
+        g.load_dense_weights(W)
+    g.close()
