@@ -1,12 +1,19 @@
 """Benchmark: synaptic events per second of the LIF-with-delays simulation on
-one MI355X, with the HBM roofline fraction of the dominant kernel and the CPU
+one MI355X, with the roofline fraction of the dominant kernel and the CPU
 oracle timed beside it.
 
 One benchmark step = one full simulation of the workload (state reset, then
 all T time steps of delivery + neuron update) on inputs already resident in
-device memory.  The default workload is the large sparse net: N = 10,000
-neurons, directed Erdos-Renyi p = 0.01 (~1M synapses), delays 1..16,
-T = 1000 steps.
+device memory.  Workloads:
+
+  large_sparse (default)  N = 10,000, directed Erdos-Renyi p = 0.01 (~1M
+                          synapses), delays 1..16, T = 1000
+  large_sparse_low        the same graph with inhibition-dominated weights
+                          (firing rate ~0.2%), event-driven delivery
+  dense_trials            N = 4096 dense weights, 64 trials, delay 1,
+                          T = 1000, matrix cores
+  uneven_batch            512 independent nets, N 50..5000, T = 500: one
+                          batched persistent launch vs one run per net
 
 Prints one JSON line.
 """
@@ -23,7 +30,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix cores, TFLOP/s
 
 
 def events_of(raster_btn: np.ndarray, out_degree: np.ndarray) -> int:
@@ -33,10 +41,162 @@ def events_of(raster_btn: np.ndarray, out_degree: np.ndarray) -> int:
 
 
 def algorithmic_bytes_per_step(events: int, steps: int, n: int, trials: int) -> float:
-    """Bytes a delivery + update step must move at minimum: one 8-byte record
-    (weight, source index and delay) per synaptic event, plus the neuron
-    state read and written (V 4+4 bytes, refractory counter 1+1) per neuron."""
+    """Bytes a delivery + update time step must move at minimum: one 8-byte
+    record (weight, source index and delay) per synaptic event, plus the
+    neuron state read and written (V 4 + 4 bytes, refractory counter 1 + 1)
+    per neuron and trial."""
     return 8.0 * events / steps + 10.0 * n * trials
+
+
+def timed(fn, stream, warmup, steps):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall
+
+
+def cpu_threads_used():
+    return 1
+
+
+def bench_single(args, net, kind):
+    """One net (possibly many trials): reset + run(T) per benchmark step."""
+    from paper_2305_02510_amd import Network
+    T = net.steps
+    g = Network.from_workload(net)
+    g.set_path(args.path)
+
+    def one_run():
+        g.reset_state()
+        g.run(T)
+
+    ms, wall = timed(one_run, g.stream, args.warmup, args.steps)
+    raster = g.read_raster(0, T)
+    V, ref = g.read_state()
+    path = g.progress[1]
+    g.close()
+    ev = events_of(raster, net.out_degree())
+    out = {"value": ev / (ms / 1e3), "ms_per_step": ms, "wall": wall, "events_per_run": ev,
+           "mean_firing_rate": float(raster.mean()), "path": path,
+           "neuron_updates_per_s": net.n * net.trials * T / (ms / 1e3)}
+    sec_per_tstep = ms / 1e3 / T
+    if kind == "dense":
+        flops = 2.0 * net.trials * net.n * net.n
+        achieved = flops / sec_per_tstep / 1e12
+        w_bytes = 2.0 * net.n * net.n
+        out["roofline"] = {
+            "bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / BF16_PEAK_TFLOPS, 5), "traffic": None, "kernel": "k_dense_step",
+            "flops_per_time_step": flops, "us_per_time_step": round(sec_per_tstep * 1e6, 3),
+            "weight_stream_GBps": round(w_bytes / sec_per_tstep / 1e9, 1),
+            "weight_stream_frac_of_hbm": round(w_bytes / sec_per_tstep / 1e9 / HBM_PEAK_GBS, 4)}
+    else:
+        bytes_step = algorithmic_bytes_per_step(ev, T, net.n, net.trials)
+        achieved = bytes_step / sec_per_tstep / 1e9
+        kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)", "step": "k_step",
+                  "push": "k_push"}.get(path, path)
+        out["roofline"] = {
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": kernel,
+            "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3)}
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.default()
+        trials = list(range(min(net.trials, args.cpu_trials)))
+        c0 = time.perf_counter()
+        res = orc.run_dense(net, trials=trials) if kind == "dense" else orc.run_sparse(net, trials=trials)
+        csec = time.perf_counter() - c0
+        ev_cpu = events_of(res.spikes, net.out_degree())
+        out["cpu_baseline"] = {
+            "value": round(ev_cpu / csec, 1), "unit": "synaptic events/s", "cores": cpu_threads_used(),
+            "kind": "oracle",
+            "sample": f"{len(trials)} of {net.trials} trial(s), all {T} steps, N={net.n}, nnz={net.nnz}: "
+                      f"{csec:.2f} s single-threaded"}
+        out["parity_bit_exact"] = bool(
+            np.array_equal(raster[trials], res.spikes) and np.array_equal(V[trials].astype(np.float64), res.V)
+            and np.array_equal(ref[trials].astype(np.int32), res.ref))
+        out["parity_sample"] = f"trials {trials}"
+    return out
+
+
+def bench_batch(args):
+    """512 uneven nets: one batched persistent launch per benchmark step,
+    compared with one run per net (each net on its own best single-net path,
+    one after another on the same stream)."""
+    from paper_2305_02510_amd import Batch, Network
+    from paper_2305_02510_amd import workloads as wl
+    nets = wl.uneven_batch(4)
+    T = nets[0].steps
+    gs = [Network.from_workload(net) for net in nets]
+    batch = Batch(gs)
+    stream = gs[0].stream
+
+    def batched():
+        for g in gs:
+            g.reset_state()
+        batch.run(T)
+
+    def plain():
+        for g in gs:
+            g.reset_state()
+            g.run(T)
+
+    ms_b, wall = timed(batched, stream, args.warmup, args.steps)
+    rasters = [g.read_raster(0, T) for g in gs]
+    states = [g.read_state() for g in gs]
+    ms_p, _ = timed(plain, stream, 1, max(1, args.steps // 2))
+    ev = sum(events_of(r, net.out_degree()) for r, net in zip(rasters, nets))
+    nnz = sum(net.nnz for net in nets)
+    neurons = sum(net.n for net in nets)
+    sec_per_tstep = ms_b / 1e3 / T
+    bytes_step = 8.0 * ev / T + 10.0 * neurons
+    achieved = bytes_step / sec_per_tstep / 1e9
+    out = {"value": ev / (ms_b / 1e3), "ms_per_step": ms_b, "wall": wall, "events_per_run": ev,
+           "mean_firing_rate": float(np.mean([r.mean() for r in rasters])), "path": "batch",
+           "neuron_updates_per_s": neurons * T / (ms_b / 1e3),
+           "plain_ms_per_run": round(ms_p, 4), "batched_speedup_vs_plain": round(ms_p / ms_b, 3),
+           "nets": len(nets), "total_neurons": neurons, "total_synapses": nnz}
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_batch",
+        "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3),
+        "streamed_record_GBps": round(8.0 * nnz / sec_per_tstep / 1e9, 1)}
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.default()
+        order = np.argsort([net.nnz for net in nets])
+        picks = sorted(set([int(order[0]), int(order[len(order) // 2]), int(order[-1])] +
+                           [int(i) for i in order[:: max(1, len(order) // 6)]]))
+        c0 = time.perf_counter()
+        ok = True
+        ev_cpu = 0
+        for i in picks:
+            res = orc.run_sparse(nets[i])
+            ev_cpu += events_of(res.spikes, nets[i].out_degree())
+            ok &= bool(np.array_equal(rasters[i], res.spikes)
+                       and np.array_equal(states[i][0].astype(np.float64), res.V)
+                       and np.array_equal(states[i][1].astype(np.int32), res.ref))
+        csec = time.perf_counter() - c0
+        out["cpu_baseline"] = {
+            "value": round(ev_cpu / csec, 1), "unit": "synaptic events/s", "cores": cpu_threads_used(),
+            "kind": "oracle", "sample": f"{len(picks)} of {len(nets)} nets (smallest, median, largest and every "
+                                        f"~{len(order) // 6}th by size), all {T} steps: {csec:.2f} s single-threaded"}
+        out["parity_bit_exact"] = ok
+        out["parity_sample"] = f"nets {picks}"
+    batch.close()
+    for g in gs:
+        g.close()
+    return out
 
 
 def main():
@@ -45,92 +205,48 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_sparse",
-                    choices=["large_sparse", "single_lif", "large_sparse_low"])
+                    choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch"])
     ap.add_argument("--path", default="auto")
+    ap.add_argument("--cpu-trials", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is "
-                          "described in DESIGN.md but not built"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; how the simulation would shard "
+                                   "across GPUs is described in DESIGN.md but not built"}))
         sys.exit(2)
 
     import torch
-    from paper_2305_02510_amd import Network
     from paper_2305_02510_amd import workloads as wl
-
     torch.cuda.set_device(0)
-    net = wl.by_name(args.workload)
-    T = net.steps
-    g = Network.from_workload(net)
-    g.set_path(args.path)
-    stream = g.stream
 
-    def one_run():
-        g.reset_state()
-        g.run(T)
-
-    for _ in range(args.warmup):
-        one_run()
-    g.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
-        one_run()
-    stop.record(stream)
-    g.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = start.elapsed_time(stop)
-    ms_per_step = gpu_ms / args.steps
-
-    raster = g.read_raster(0, T)
-    V, ref = g.read_state()
-    path = g.progress[1]
-    g.close()
-    outdeg = net.out_degree()
-    ev = events_of(raster, outdeg)
-    value = ev / (ms_per_step / 1e3)
-    rate = float(raster.mean())
-
-    # roofline of the dominant kernel: algorithmic bytes of one time step over
-    # the average time of one time step inside the timed region
-    bytes_step = algorithmic_bytes_per_step(ev, T, net.n, net.trials)
-    sec_per_tstep = ms_per_step / 1e3 / T
-    achieved = bytes_step / sec_per_tstep / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": {"step": "k_step", "small": "k_small"}.get(path, path),
-                "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3)}
-
-    cpu = None
-    parity = None
-    if not args.no_cpu_baseline:
-        import oracle
-        orc = oracle.default()
-        c0 = time.perf_counter()
-        res = orc.run_sparse(net)
-        csec = time.perf_counter() - c0
-        cpu = {"value": round(ev / csec, 1), "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full run of the workload ({T} steps, N={net.n}, nnz={net.nnz}), "
-                         f"{csec:.2f} s single-threaded"}
-        parity = bool(np.array_equal(raster, res.spikes) and np.array_equal(V.astype(np.float64), res.V)
-                      and np.array_equal(ref.astype(np.int32), res.ref))
-
+    if args.workload == "uneven_batch":
+        r = bench_batch(args)
+        desc = (f"uneven_batch: {r['nets']} independent nets, N log-uniform 50..5000 (total {r['total_neurons']}), "
+                f"p 0.005..0.2 (total {r['total_synapses']} synapses), D 1..16, T=500")
+        cfg = {"workload": desc, "nets": r["nets"], "time_steps_per_run": 500}
+    else:
+        net = wl.by_name(args.workload)
+        kind = "dense" if args.workload == "dense_trials" else "sparse"
+        r = bench_single(args, net, kind)
+        cfg = {"workload": f"{net.name}: N={net.n}, nnz={net.nnz}, D={net.max_delay}, T={net.steps}, "
+                           f"trials={net.trials}", "time_steps_per_run": net.steps, "trials": net.trials}
+    cfg["path"] = r["path"]
     out = {
-        "metric": "synaptic events/sec", "value": round(value, 1), "unit": "synaptic events/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded Erdos-Renyi net and Bernoulli external spikes)",
-        "config": {"workload": f"{net.name}: N={net.n}, nnz={net.nnz}, D={net.max_delay}, T={T}, "
-                               f"trials={net.trials}", "path": path, "time_steps_per_run": T},
-        "neuron_updates_per_s": round(net.n * net.trials * T / (ms_per_step / 1e3), 1),
-        "events_per_run": ev, "mean_firing_rate": round(rate, 5),
-        "roofline": roofline, "cpu_baseline": cpu, "parity_bit_exact": parity,
-        "wall_s_timed": round(wall, 4),
+        "metric": "synaptic events/sec", "value": round(r["value"], 1), "unit": "synaptic events/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 x bf16 -> f32" if args.workload == "dense_trials" else "f32",
+        "data": "synthetic (seeded Erdos-Renyi / dense nets and Bernoulli external spikes)",
+        "config": cfg,
+        "neuron_updates_per_s": round(r["neuron_updates_per_s"], 1),
+        "events_per_run": r["events_per_run"], "mean_firing_rate": round(r["mean_firing_rate"], 5),
+        "roofline": r["roofline"], "cpu_baseline": r.get("cpu_baseline"),
+        "parity_bit_exact": r.get("parity_bit_exact"), "parity_sample": r.get("parity_sample"),
+        "wall_s_timed": round(r["wall"], 4),
     }
+    for k in ("plain_ms_per_run", "batched_speedup_vs_plain"):
+        if k in r:
+            out[k] = r[k]
     print(json.dumps(out), flush=True)
 
 

@@ -70,7 +70,8 @@ enum {
   SN_PATH_SMALL = 1,    /* one workgroup per trial runs all requested steps in one launch */
   SN_PATH_STEP = 2,     /* one launch per step: pull delivery over post-neuron groups */
   SN_PATH_PERSIST = 3,  /* one cooperative launch for all steps, grid barrier per step */
-  SN_PATH_DENSE = 4     /* dense weights on matrix cores (needs sn_load_dense_weights) */
+  SN_PATH_DENSE = 4,    /* dense weights on matrix cores (needs sn_load_dense_weights) */
+  SN_PATH_PUSH = 5      /* event-driven: only synapses of spiking neurons are touched (low firing rates) */
 };
 
 /* Device-memory allocator.  alloc returns device memory of at least `bytes`
@@ -176,14 +177,43 @@ sn_status sn_set_path(sn_net* net, int32_t path);
 
 /* Number of slices (workgroups per trial) of SN_PATH_PERSIST: 0 picks the
  * fewest slices whose synapse records fit in on-chip memory (or one per
- * compute unit when they cannot); 1..256 forces a count (clamped to the
- * number of 64-neuron groups).  A tuning knob: results do not change.
+ * compute unit when they cannot); 1..256 requests a count, raised to the
+ * minimum a slice can hold (128 groups of 64 neurons per slice) and lowered
+ * to the number of groups.  A tuning knob: results do not change.
  * Errors: SN_ERANGE. */
 sn_status sn_set_slices(sn_net* net, int32_t slices);
 
 /* Reports the number of simulated steps so far (*t) and the strategy the
  * last sn_run used (*path, SN_PATH_AUTO before the first run). */
 sn_status sn_get_progress(sn_net* net, int32_t* t, int32_t* path);
+
+/* ---- Batched execution of many independent networks --------------------
+ * A batch runs its networks together in one persistent launch: networks too
+ * large for one workgroup are split across a team of workgroups, the others
+ * are taken one at a time from a device work queue by free workgroups.  Each
+ * network keeps its own state, history and inputs and stays readable with
+ * sn_read_raster / sn_read_state; results equal separate sn_run calls.
+ * All networks must be on the same device, have synapses loaded, and have no
+ * unfinished work on other streams; the batch uses the first network's
+ * stream.  Networks may have different sizes, delays, trial counts and step
+ * counters.  The batch holds no reference count: destroy it before its
+ * networks.  Limits: N <= 2048 * (number of compute units), spike ring
+ * (D + 1) * ceil(N/32) * 4 bytes <= 96 KB per network. */
+typedef struct sn_batch sn_batch;
+
+/* Plans a batch over nets[0 .. count-1].  Errors: SN_EINVAL (null or
+ * duplicate networks), SN_ESTATE (a network without synapses or poisoned),
+ * SN_ERANGE (a network outside the limits, or count outside [1, 65536]),
+ * SN_ENOMEM, SN_EDEVICE. */
+sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out);
+
+/* Advances every network of the batch by n_steps steps, asynchronously on
+ * the batch's stream.  Errors: SN_ERANGE, SN_ENOMEM, SN_EDEVICE (poisons the
+ * batch and its networks). */
+sn_status sn_batch_run(sn_batch* batch, int32_t n_steps);
+
+/* Frees the batch (not its networks).  NULL is ignored. */
+void sn_batch_destroy(sn_batch* batch);
 
 /* Frees the network and its device memory after its work has finished.
  * NULL is ignored. */

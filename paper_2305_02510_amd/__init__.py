@@ -5,4 +5,4 @@ The simulation runs in the HIP library ``libsnmi.so`` (C ABI in
 ``include/superneuro_mi.h``); ``Network`` marshals arguments to it, with
 PyTorch providing device memory and the stream.
 """
-from .network import Network, pack_bits, unpack_bits  # noqa: F401
+from .network import Batch, Network, pack_bits, unpack_bits  # noqa: F401

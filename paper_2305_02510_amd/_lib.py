@@ -10,14 +10,15 @@ LIB_PATH = os.path.join(HERE, "libsnmi.so")
 SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ESTATE, SN_ERANGE, SN_EINEXACT = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "SN_OK", -1: "SN_EINVAL", -2: "SN_ENOMEM", -3: "SN_EDEVICE", -4: "SN_ESTATE",
                 -5: "SN_ERANGE", -6: "SN_EINEXACT"}
-PATH_AUTO, PATH_SMALL, PATH_STEP, PATH_PERSIST, PATH_DENSE = 0, 1, 2, 3, 4
-PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense"}
+PATH_AUTO, PATH_SMALL, PATH_STEP, PATH_PERSIST, PATH_DENSE, PATH_PUSH = 0, 1, 2, 3, 4, 5
+PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense", 5: "push", 6: "batch"}
 
 # Every symbol the header declares.
 EXPORTS = [
     "sn_create_network", "sn_load_weights_delays", "sn_load_dense_weights", "sn_set_input_spikes",
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_get_progress", "sn_destroy_network", "sn_last_error",
+    "sn_batch_create", "sn_batch_run", "sn_batch_destroy",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -72,6 +73,8 @@ def load():
         "sn_set_path": [P, I32],
         "sn_set_slices": [P, I32],
         "sn_get_progress": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "sn_batch_create": [P, I32, ctypes.POINTER(P)],
+        "sn_batch_run": [P, I32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -79,6 +82,8 @@ def load():
         fn.restype = ctypes.c_int32
     lib.sn_destroy_network.argtypes = [P]
     lib.sn_destroy_network.restype = None
+    lib.sn_batch_destroy.argtypes = [P]
+    lib.sn_batch_destroy.restype = None
     lib.sn_last_error.argtypes = []
     lib.sn_last_error.restype = ctypes.c_char_p
     _lib = lib

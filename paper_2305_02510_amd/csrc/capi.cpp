@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -58,8 +59,24 @@ struct sn_net {
     bool ok = false;
   };
   DevPlan small, persist;
+  // event-driven delivery: out-going records, accumulator ring, flags
+  void* orecs = nullptr;
+  void* optr = nullptr;
+  void* push_wg = nullptr;
+  float* accum = nullptr;
+  uint32_t* push_flags = nullptr;
+  int32_t push_P = 0, push_ng_max = 0;
+  // dense matrix-core weights (sn_load_dense_weights)
+  void* wt = nullptr;
+  int32_t kpad = 0;
+  bool dense_loaded = false;
+  // cached graph of per-step launches
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int32_t graph_path = -1, graph_t0 = -1, graph_steps = -1;
+  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t slices_req = 0;
-  uint32_t* flags = nullptr;  // [B][256]
+  uint64_t* mailbox = nullptr;  // [D + 1][B][2G] tagged spike words
   uint32_t* status = nullptr;
   HostLayout layout;          // kept to re-plan when the slice count changes
 };
@@ -159,7 +176,9 @@ SlicePlan plan_persist(const DevNet& d, const HostLayout& L, int32_t slices_req)
   const int32_t pmax = std::max(1, kMaxCoopGroups / d.B);
   const int32_t top = std::min(d.G, pmax);
   if (slices_req > 0) {
-    SlicePlan p = partition_groups(L, d.G, std::min(slices_req, top), 128);
+    // a slice holds at most 128 groups (8 per wave of a 1024-thread workgroup)
+    const int32_t lo_req = std::max(slices_req, (d.G + 127) / 128);
+    SlicePlan p = partition_groups(L, d.G, std::min(lo_req, top), 128);
     if (!fit_plan(d, p)) p.P = 0;
     return p;
   }
@@ -204,7 +223,7 @@ SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
   a.n = n->d;
   a.wg_group = static_cast<const int32_t*>(dp.wg);
   a.wg_chunk = static_cast<const int32_t*>(dp.wg) + dp.host.P + 1;
-  a.flags = n->flags;
+  a.mailbox = n->mailbox;
   a.status = n->status;
   a.P = dp.host.P;
   a.ng_max = dp.host.ng_max;
@@ -218,10 +237,98 @@ sn_status check_status(sn_net* n) {
   SN_HIP(n, hipMemcpy(&st, n->status, sizeof(st), hipMemcpyDeviceToHost));
   if (st != 0) {
     n->poisoned = true;
-    return fail(SN_EDEVICE, "a grid-barrier wait of the persistent kernel timed out");
+    return fail(SN_EDEVICE, "a spike-exchange wait of the persistent kernel timed out");
   }
   return SN_OK;
 }
+
+// Launches steps t0 .. t0+steps-1 of a per-step path, through a cached HIP
+// graph when the run is long enough to amortise the capture.
+sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
+  auto launch_all = [&](hipStream_t s) -> hipError_t {
+    for (int32_t k = 0; k < steps; ++k) {
+      hipError_t e;
+      if (path == SN_PATH_DENSE) {
+        DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad};
+        e = launch_dense_step(a, t0 + k, s);
+      } else {
+        e = launch_step(n->d, t0 + k, s);
+      }
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  if (steps < 32) {
+    SN_HIP(n, launch_all(n->stream));
+    return SN_OK;
+  }
+  const void* key[4] = {n->d.raster, n->d.ext, n->d.recs, n->wt};
+  const bool hit = n->graph && n->graph_path == path && n->graph_t0 == t0 && n->graph_steps == steps &&
+                   std::equal(key, key + 4, n->graph_key);
+  if (!hit) {
+    if (n->graph) {
+      SN_HIP(n, hipGraphExecDestroy(n->graph));
+      n->graph = nullptr;
+    }
+    if (!n->capture_stream) SN_HIP(n, hipStreamCreateWithFlags(&n->capture_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    SN_HIP(n, hipStreamBeginCapture(n->capture_stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = launch_all(n->capture_stream);
+    const hipError_t ce = hipStreamEndCapture(n->capture_stream, &g);
+    if (le != hipSuccess) return device_error(n, le, "kernel launch during graph capture");
+    if (ce != hipSuccess) return device_error(n, ce, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&n->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return device_error(n, ie, "hipGraphInstantiate");
+    n->graph_path = path;
+    n->graph_t0 = t0;
+    n->graph_steps = steps;
+    std::copy(key, key + 4, n->graph_key);
+  }
+  SN_HIP(n, hipGraphLaunch(n->graph, n->stream));
+  return SN_OK;
+}
+
+// Event-driven path: slices of whole groups, one workgroup per CU at most.
+sn_status run_push(sn_net* n, int32_t t0, int32_t steps) {
+  if (!n->push_wg) {
+    const int32_t P = std::max(1, std::min(n->d.G, kMaxCoopGroups / n->d.B));
+    std::vector<int32_t> wg(P + 1);
+    for (int32_t w = 0; w <= P; ++w) wg[w] = static_cast<int32_t>(static_cast<int64_t>(n->d.G) * w / P);
+    int32_t ng_max = 0;
+    for (int32_t w = 0; w < P; ++w) ng_max = std::max(ng_max, wg[w + 1] - wg[w]);
+    const size_t acc_bytes = static_cast<size_t>(n->d.D + 1) * n->d.B * n->d.Npad * sizeof(float);
+    const size_t flag_bytes = static_cast<size_t>(n->d.B) * P * 64 * sizeof(uint32_t);
+    void* wgp = dev_alloc(n, wg.size() * sizeof(int32_t));
+    void* acc = dev_alloc(n, acc_bytes + flag_bytes);
+    if (!wgp || !acc) {
+      dev_free(n, wgp);
+      dev_free(n, acc);
+      return fail(SN_ENOMEM, "cannot allocate the accumulator ring");
+    }
+    SN_HIP(n, hipMemcpyAsync(wgp, wg.data(), wg.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+    SN_HIP(n, hipStreamSynchronize(n->stream));
+    n->push_wg = wgp;
+    n->accum = static_cast<float*>(acc);
+    n->push_flags = reinterpret_cast<uint32_t*>(static_cast<char*>(acc) + acc_bytes);
+    n->push_P = P;
+    n->push_ng_max = ng_max;
+  }
+  PushArgs a{};
+  a.n = n->d;
+  a.orecs = static_cast<const Rec*>(n->orecs);
+  a.optr = static_cast<const int32_t*>(n->optr);
+  a.wg_group = static_cast<const int32_t*>(n->push_wg);
+  a.accum = n->accum;
+  a.flags = n->push_flags;
+  a.status = n->status;
+  a.P = n->push_P;
+  a.ng_max = n->push_ng_max;
+  SN_HIP(n, launch_push(a, t0, steps, n->stream));
+  return SN_OK;
+}
+
+constexpr int32_t kPathBatch = 6;  // sn_get_progress after a batch run
 
 bool on_device_ok(sn_net* n) {
   int cur = -1;
@@ -230,9 +337,235 @@ bool on_device_ok(sn_net* n) {
 
 }  // namespace
 
+struct sn_batch {
+  std::vector<sn_net*> nets;
+  hipStream_t stream = nullptr;
+  std::vector<SlicePlan> plans;  // per network: team plan (P > 1) or one slice
+  void* plan_buf = nullptr;      // device copy of every plan's slice tables
+  std::vector<size_t> plan_off;  // int32 offset of each network's tables in plan_buf
+  std::vector<int4> team, queue; // task templates (t0 filled at run time)
+  std::vector<BatchNet> descs;
+  void* nets_buf = nullptr;
+  void* team_buf = nullptr;
+  void* queue_buf = nullptr;
+  void* head_buf = nullptr;
+  int grid = 0;
+  size_t lds = 0;
+  bool poisoned = false;
+};
+
+namespace {
+
+void batch_free(sn_batch* bt) {
+  if (bt->nets.empty()) return;
+  sn_net* a = bt->nets[0];
+  dev_free(a, bt->plan_buf);
+  dev_free(a, bt->nets_buf);
+  dev_free(a, bt->team_buf);
+  dev_free(a, bt->queue_buf);
+  dev_free(a, bt->head_buf);
+  bt->plan_buf = bt->nets_buf = bt->team_buf = bt->queue_buf = bt->head_buf = nullptr;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sn_last_error(void) { return g_err.c_str(); }
+
+sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
+  if (!nets || !out) return fail(SN_EINVAL, "nets and out must not be NULL");
+  *out = nullptr;
+  if (count < 1 || count > 65536) return fail(SN_ERANGE, "count %d outside [1, 65536]", count);
+  std::vector<sn_net*> v(nets, nets + count);
+  {
+    std::vector<sn_net*> sorted(v);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return fail(SN_EINVAL, "a network appears twice");
+  }
+  for (int32_t k = 0; k < count; ++k) {
+    sn_net* n = v[k];
+    if (!n) return fail(SN_EINVAL, "network %d is NULL", k);
+    if (n->poisoned) return fail(SN_ESTATE, "network %d is poisoned", k);
+    if (!n->synapses_loaded) return fail(SN_ESTATE, "network %d has no synapses", k);
+    if (n->device != v[0]->device) return fail(SN_EINVAL, "networks are on different devices");
+    if (batch_lds_bytes(n->d, 0) > 96 * 1024) return fail(SN_ERANGE, "network %d: spike ring too large for a batch", k);
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v[0]->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SN_EDEVICE, "cannot query the device");
+  }
+  // cost of one step of one trial: records streamed plus neuron updates
+  std::vector<double> cost(count);
+  double total = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    cost[k] = static_cast<double>(v[k]->d.nnz) + 4.0 * v[k]->d.Npad;
+    total += cost[k] * v[k]->d.B;
+  }
+  sn_batch* bt = new (std::nothrow) sn_batch();
+  if (!bt) return fail(SN_ENOMEM, "out of host memory");
+  bt->nets = v;
+  bt->stream = v[0]->stream;
+  // workgroups resident at once, for the largest LDS any network needs
+  size_t lds = 0;
+  for (sn_net* n : v) lds = std::max(lds, batch_lds_bytes(n->d, std::min<int32_t>(n->d.G, kBatchMaxGroups)));
+  const int per_cu = batch_blocks_per_cu(lds);
+  if (per_cu < 1) {
+    delete bt;
+    return fail(SN_ERANGE, "batch kernel does not fit on a compute unit");
+  }
+  bt->grid = per_cu * cus;
+  // team sizes: no slice above ~the average load; teams use at most 3/4 of the workgroups
+  double target = total / bt->grid;
+  std::vector<int32_t> P(count);
+  for (int iter = 0; iter < 64; ++iter) {
+    int64_t team_wgs = 0;
+    for (int32_t k = 0; k < count; ++k) {
+      const int32_t G = v[k]->d.G;
+      int32_t p = std::max<int32_t>((G + kBatchMaxGroups - 1) / kBatchMaxGroups,
+                                    static_cast<int32_t>(std::ceil(cost[k] / target)));
+      p = std::min(p, G);
+      P[k] = p;
+      if (p > 1) team_wgs += static_cast<int64_t>(p) * v[k]->d.B;
+    }
+    if (team_wgs <= (3 * static_cast<int64_t>(bt->grid)) / 4) break;
+    target *= 1.25;
+  }
+  // slice plans and their device tables
+  bt->plans.resize(count);
+  bt->plan_off.resize(count);
+  std::vector<int32_t> tables;
+  lds = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    sn_net* n = v[k];
+    SlicePlan p = partition_groups(n->layout, n->d.G, P[k], kBatchMaxGroups);
+    if (p.ng_max > kBatchMaxGroups) {
+      delete bt;
+      return fail(SN_ERANGE, "network %d: too many neurons for a batch", k);
+    }
+    bt->plan_off[k] = tables.size();
+    tables.insert(tables.end(), p.wg_group.begin(), p.wg_group.end());
+    tables.insert(tables.end(), p.wg_chunk.begin(), p.wg_chunk.end());
+    lds = std::max(lds, batch_lds_bytes(n->d, p.ng_max));
+    bt->plans[k] = std::move(p);
+  }
+  bt->lds = lds;
+  // tasks: teams first (largest first, slices of a team contiguous), then the queue
+  std::vector<int32_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  for (int32_t k : order) {
+    if (bt->plans[k].P > 1) {
+      for (int32_t b = 0; b < v[k]->d.B; ++b)
+        for (int32_t w = 0; w < bt->plans[k].P; ++w) bt->team.push_back(make_int4(k, w, b, 0));
+    } else {
+      for (int32_t b = 0; b < v[k]->d.B; ++b) bt->queue.push_back(make_int4(k, b, 0, 0));
+    }
+  }
+  if (static_cast<int64_t>(bt->team.size()) > bt->grid) {
+    delete bt;
+    return fail(SN_ERANGE, "batch teams need more workgroups than the device holds");
+  }
+  sn_net* a = v[0];
+  bt->plan_buf = dev_alloc(a, tables.size() * sizeof(int32_t));
+  bt->nets_buf = dev_alloc(a, count * sizeof(BatchNet));
+  bt->team_buf = dev_alloc(a, std::max<size_t>(1, bt->team.size()) * sizeof(int4));
+  bt->queue_buf = dev_alloc(a, std::max<size_t>(1, bt->queue.size()) * sizeof(int4));
+  bt->head_buf = dev_alloc(a, 256);
+  if (!bt->plan_buf || !bt->nets_buf || !bt->team_buf || !bt->queue_buf || !bt->head_buf) {
+    batch_free(bt);
+    delete bt;
+    return fail(SN_ENOMEM, "cannot allocate batch tables");
+  }
+  if (hipMemcpyAsync(bt->plan_buf, tables.data(), tables.size() * sizeof(int32_t), hipMemcpyHostToDevice, bt->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(bt->stream) != hipSuccess) {
+    batch_free(bt);
+    delete bt;
+    return fail(SN_EDEVICE, "cannot upload batch tables");
+  }
+  *out = bt;
+  return SN_OK;
+}
+
+sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
+  if (!bt) return fail(SN_EINVAL, "batch is NULL");
+  if (bt->poisoned) return fail(SN_ESTATE, "batch is poisoned by an earlier device error");
+  if (n_steps < 0) return fail(SN_ERANGE, "n_steps must be >= 0");
+  if (n_steps == 0) return SN_OK;
+  const int32_t count = static_cast<int32_t>(bt->nets.size());
+  for (sn_net* n : bt->nets) {
+    sn_status st = check_usable(n);
+    if (st != SN_OK) return st;
+    if (static_cast<int64_t>(n->t) + n_steps > INT32_MAX) return fail(SN_ERANGE, "step counter overflows");
+  }
+  auto poison = [&](hipError_t e, const char* what) {
+    bt->poisoned = true;
+    for (sn_net* n : bt->nets) n->poisoned = true;
+    return fail(SN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  };
+  for (sn_net* n : bt->nets) {
+    sn_status st = ensure_rows(n, static_cast<int64_t>(n->t) + n_steps);
+    if (st != SN_OK) return st;
+    if (n->stream != bt->stream) {
+      const hipError_t e = hipStreamSynchronize(n->stream);
+      if (e != hipSuccess) return poison(e, "hipStreamSynchronize");
+    }
+  }
+  const int32_t* tables = static_cast<const int32_t*>(bt->plan_buf);
+  bt->descs.resize(count);
+  for (int32_t k = 0; k < count; ++k) {
+    sn_net* n = bt->nets[k];
+    const SlicePlan& p = bt->plans[k];
+    SimArgs a{};
+    a.n = n->d;
+    a.wg_group = tables + bt->plan_off[k];
+    a.wg_chunk = tables + bt->plan_off[k] + p.P + 1;
+    a.mailbox = n->mailbox;
+    a.status = n->status;
+    a.P = p.P;
+    a.ng_max = p.ng_max;
+    a.max_recs = p.max_recs;
+    bt->descs[k].team = a;
+    bt->descs[k].single = a;
+    if (p.P > 1) {
+      const hipError_t e = launch_prefill_mailbox(a, n->t, bt->stream);
+      if (e != hipSuccess) return poison(e, "mailbox prefill");
+    }
+  }
+  for (int4& x : bt->team) x.w = bt->nets[x.x]->t;
+  for (int4& x : bt->queue) x.z = bt->nets[x.x]->t;
+  hipError_t e = hipMemcpyAsync(bt->nets_buf, bt->descs.data(), count * sizeof(BatchNet), hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess && !bt->team.empty())
+    e = hipMemcpyAsync(bt->team_buf, bt->team.data(), bt->team.size() * sizeof(int4), hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess && !bt->queue.empty())
+    e = hipMemcpyAsync(bt->queue_buf, bt->queue.data(), bt->queue.size() * sizeof(int4), hipMemcpyHostToDevice, bt->stream);
+  if (e != hipSuccess) return poison(e, "batch table upload");
+  e = launch_zero_i32(static_cast<int32_t*>(bt->head_buf), bt->stream);
+  if (e != hipSuccess) return poison(e, "queue reset");
+  BatchArgs ba{};
+  ba.nets = static_cast<const BatchNet*>(bt->nets_buf);
+  ba.team = static_cast<const int4*>(bt->team_buf);
+  ba.queue = static_cast<const int4*>(bt->queue_buf);
+  ba.n_team = static_cast<int32_t>(bt->team.size());
+  ba.n_queue = static_cast<int32_t>(bt->queue.size());
+  ba.queue_head = static_cast<int32_t*>(bt->head_buf);
+  e = launch_batch(ba, bt->grid, bt->lds, n_steps, bt->stream);
+  if (e != hipSuccess) return poison(e, "batch launch");
+  for (sn_net* n : bt->nets) {
+    n->t += n_steps;
+    n->last_path = kPathBatch;
+  }
+  return SN_OK;
+}
+
+void sn_batch_destroy(sn_batch* bt) {
+  if (!bt) return;
+  (void)hipStreamSynchronize(bt->stream);
+  batch_free(bt);
+  delete bt;
+}
 
 sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc, void* hip_stream, sn_net** out) {
   if (!desc || !out) return fail(SN_EINVAL, "desc and out must not be NULL");
@@ -295,11 +628,12 @@ sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc, 
   if (R) n->owned.push_back(R);
   n->d.V = static_cast<float*>(V);
   n->d.ref = static_cast<uint8_t*>(R);
-  void* F = dev_alloc(n, static_cast<size_t>(B) * kMaxCoopGroups * sizeof(uint32_t) + 256);
+  const size_t mail_bytes = static_cast<size_t>(D + 1) * B * 2 * G * sizeof(uint64_t);
+  void* F = dev_alloc(n, mail_bytes + 256);
   if (F) n->owned.push_back(F);
-  n->flags = static_cast<uint32_t*>(F);
-  n->status = F ? reinterpret_cast<uint32_t*>(static_cast<char*>(F) + static_cast<size_t>(B) * kMaxCoopGroups * 4) : nullptr;
-  if (F && hipMemsetAsync(F, 0, static_cast<size_t>(B) * kMaxCoopGroups * sizeof(uint32_t) + 256, n->stream) != hipSuccess) F = nullptr;
+  n->mailbox = static_cast<uint64_t*>(F);
+  n->status = F ? reinterpret_cast<uint32_t*>(static_cast<char*>(F) + mail_bytes) : nullptr;
+  if (F && hipMemsetAsync(F, 0, mail_bytes + 256, n->stream) != hipSuccess) F = nullptr;
   if (!n->d.theta || !n->d.leak || !n->d.reset || !n->d.amp || !n->d.refr || !V || !R || !F) {
     sn_destroy_network(n);
     return fail(SN_ENOMEM, "cannot allocate or upload neuron arrays");
@@ -362,9 +696,30 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->d.recs = static_cast<const Rec*>(recs);
   n->d.gptr = static_cast<const int32_t*>(gptr);
   n->d.chunks = static_cast<const uint2*>(chunks);
+  {
+    HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
+    void* orecs = dev_alloc(n, H.orecs.size() * sizeof(Rec));
+    void* optr = dev_alloc(n, H.optr.size() * sizeof(int32_t));
+    if (!orecs || !optr) {
+      dev_free(n, orecs);
+      dev_free(n, optr);
+      return fail(SN_ENOMEM, "cannot allocate out-going synapse records");
+    }
+    dev_free(n, n->orecs);
+    dev_free(n, n->optr);
+    n->orecs = orecs;
+    n->optr = optr;
+    if (!H.orecs.empty())
+      SN_HIP(n, hipMemcpyAsync(orecs, H.orecs.data(), H.orecs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
+    SN_HIP(n, hipMemcpyAsync(optr, H.optr.data(), H.optr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+    SN_HIP(n, hipStreamSynchronize(n->stream));
+  }
   n->d.nnz = nnz;
   n->d.nchunks = static_cast<int32_t>(L.chunks.size());
   n->synapses_loaded = true;
+  dev_free(n, n->wt);
+  n->wt = nullptr;
+  n->dense_loaded = false;
   SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
   if (!fit_plan(n->d, one)) one.P = 0;
   st = upload_plan(n, n->small, one);
@@ -389,7 +744,10 @@ sn_status sn_load_dense_weights(sn_net* n, const float* W, int32_t delay) {
   if (st != SN_OK) return st;
   if (!W) return fail(SN_EINVAL, "W must not be NULL");
   if (delay != 1) return fail(SN_ERANGE, "dense weights support delay 1 only (got %d)", delay);
+  if (delay > n->d.D) return fail(SN_ERANGE, "delay %d exceeds max_delay %d", delay, n->d.D);
   const int32_t N = n->d.N;
+  const int32_t kpad = (n->d.Npad + 127) / 128 * 128;
+  if (dense_lds_bytes(kpad) > lds_limit()) return fail(SN_ERANGE, "dense path supports up to 16,384 neurons");
   std::vector<int32_t> pre, post;
   std::vector<float> w;
   for (int32_t i = 0; i < N; ++i) {
@@ -407,7 +765,19 @@ sn_status sn_load_dense_weights(sn_net* n, const float* W, int32_t delay) {
     }
   }
   std::vector<uint8_t> d(w.size(), 1);
-  return sn_load_weights_delays(n, static_cast<int64_t>(w.size()), pre.data(), post.data(), w.data(), d.data());
+  st = sn_load_weights_delays(n, static_cast<int64_t>(w.size()), pre.data(), post.data(), w.data(), d.data());
+  if (st != SN_OK) return st;
+  std::vector<uint16_t> tiled(dense_tiled_elems(n->d.Npad, kpad));
+  tile_dense_weights(W, N, n->d.Npad, kpad, tiled.data());
+  void* wt = dev_alloc(n, tiled.size() * sizeof(uint16_t));
+  if (!wt) return fail(SN_ENOMEM, "cannot allocate dense weights");
+  n->wt = wt;
+  n->kpad = kpad;
+  SN_HIP(n, hipMemcpyAsync(wt, tiled.data(), tiled.size() * sizeof(uint16_t), hipMemcpyHostToDevice, n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  SN_HIP(n, prepare_dense_kernel(kpad));
+  n->dense_loaded = true;
+  return SN_OK;
 }
 
 sn_status sn_set_input_spikes(sn_net* n, int32_t t0, int32_t n_steps, const uint32_t* bits) {
@@ -459,7 +829,7 @@ sn_status sn_set_input_spikes_device(sn_net* n, int32_t t0, int32_t n_steps, con
 sn_status sn_set_path(sn_net* n, int32_t path) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
-  if (path < SN_PATH_AUTO || path > SN_PATH_DENSE) return fail(SN_ERANGE, "unknown path %d", path);
+  if (path < SN_PATH_AUTO || path > SN_PATH_PUSH) return fail(SN_ERANGE, "unknown path %d", path);
   n->path = path;
   return SN_OK;
 }
@@ -486,7 +856,8 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
   if (path == SN_PATH_AUTO) {
     // one workgroup when its records and spike ring fit in LDS, otherwise one
     // launch per step
-    path = (n->small.ok && n->small.host.recs_lds && n->small.host.ring_lds) ? SN_PATH_SMALL : SN_PATH_STEP;
+    if (n->dense_loaded) path = SN_PATH_DENSE;
+    else path = (n->small.ok && n->small.host.recs_lds && n->small.host.ring_lds) ? SN_PATH_SMALL : SN_PATH_STEP;
   }
   switch (path) {
     case SN_PATH_SMALL:
@@ -496,13 +867,22 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
       break;
     case SN_PATH_PERSIST: {
       if (!n->persist.ok) return fail(SN_ERANGE, "no slice plan fits the persistent kernel");
-      SimArgs a = sim_args(n, n->persist);
-      SN_HIP(n, launch_clear_u32(n->flags, n->d.B * a.P, n->stream));
-      SN_HIP(n, launch_sim(a, n->persist.host.recs_lds, n->persist.host.ring_lds, n->t, n_steps, n->stream));
+      SN_HIP(n, launch_sim(sim_args(n, n->persist), n->persist.host.recs_lds, n->persist.host.ring_lds, n->t,
+                           n_steps, n->stream));
       break;
     }
     case SN_PATH_STEP:
-      for (int32_t k = 0; k < n_steps; ++k) SN_HIP(n, launch_step(n->d, n->t + k, n->stream));
+      st = run_per_step(n, SN_PATH_STEP, n->t, n_steps);
+      if (st != SN_OK) return st;
+      break;
+    case SN_PATH_PUSH:
+      st = run_push(n, n->t, n_steps);
+      if (st != SN_OK) return st;
+      break;
+    case SN_PATH_DENSE:
+      if (!n->dense_loaded) return fail(SN_ESTATE, "the dense path needs sn_load_dense_weights");
+      st = run_per_step(n, SN_PATH_DENSE, n->t, n_steps);
+      if (st != SN_OK) return st;
       break;
     default:
       return fail(SN_ERANGE, "path %d is not available in this build", path);
@@ -584,6 +964,13 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->chunks);
   dev_free(n, n->small.wg);
   dev_free(n, n->persist.wg);
+  dev_free(n, n->wt);
+  dev_free(n, n->orecs);
+  dev_free(n, n->optr);
+  dev_free(n, n->push_wg);
+  dev_free(n, n->accum);
+  if (n->graph) (void)hipGraphExecDestroy(n->graph);
+  if (n->capture_stream) (void)hipStreamDestroy(n->capture_stream);
   delete n;
 }
 

@@ -2,77 +2,93 @@
 // leak / integrate / threshold / refractory / reset update of §2.1.
 #include <hip/hip_runtime.h>
 
+#include "sn_device.h"
 #include "sn_internal.h"
 
 namespace snmi {
 
 // ---------------------------------------------------------------------------
-// Neuron update (§2.1, steps 1 and 3-6; step 2's sum arrives in `syn`).
-// All operands are binary32; with dyadic inputs every operation is exact.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float leak_toward(float v, float r, float lam) {
-  if (v > r) return fmaxf(v - lam, r);
-  if (v < r) return fminf(v + lam, r);
-  return v;
-}
-
-__device__ __forceinline__ bool lif_update(float& V, int& ref, float syn, bool ext, float theta, float lam,
-                                           float r, float amp, int R) {
-  float U = leak_toward(V, r, lam);
-  U = U + syn;
-  if (ext) U = U + amp;
-  const bool cand = U > theta;
-  bool s;
-  if (ref > 0) {
-    s = false;
-    ref = ref - 1;
-  } else {
-    s = cand;
-  }
-  if (s) {
-    V = r;
-    ref = R;
-  } else {
-    V = U;
-  }
-  return s;
-}
-
-__device__ __forceinline__ size_t row_word(const DevNet& n, int64_t t, int b, int g) {
-  return (static_cast<size_t>(t) * n.B + b) * n.G + g;
-}
-
-// ---------------------------------------------------------------------------
 // Persistent kernel: runs `steps` time steps in one launch.
 //
-// Workgroup (w, b) owns the contiguous post-neuron groups [g0, g1) of slice w
-// for trial b: their records (copied to LDS when they fit) and their neuron
-// state (registers).  The spike history of the last D steps is a ring of D+1
-// bit rows in LDS when it fits (slot t mod (D+1) holds step t; step t reads
-// the slots of t - d, d = 1..D, never its own), else it is read from the
-// raster in global memory.
+// Workgroup (w, b) owns the contiguous post-neuron groups [g0, g0 + ng) of
+// slice w for trial b: their records (copied to LDS when they fit) and their
+// neuron state (registers).  The spike history of the last D steps is a ring
+// of D + 1 bit rows (slot t mod (D+1) holds step t; step t reads the slots of
+// t - d, d = 1..D, never its own), in LDS when it fits.
 //
-// With several slices (MULTI), the workgroups of a trial exchange each step's
-// spike words through the raster: a workgroup writes its words, publishes
-// `flags[b][w] = t + 1` with an agent-scope release, waits until every slice
-// of its trial has published t + 1 (relaxed agent-scope polls, then an
-// agent-scope acquire fence), and copies row t into its ring.  A slice can run
-// at most one step ahead of the slowest one.  Every wait is bounded: after
-// kSpinLimit polls the workgroup records a timeout in *status and all of its
-// waves exit; the slices waiting on it then time out the same way.
+// Spike exchange.  Every step each workgroup also publishes its spike words,
+// 32 spikes per 64-bit word tagged with the step: (t + 1) << 32 | bits, stored
+// with one device-scope relaxed atomic in the mailbox ring [D+1][B][2G].
+// Because tag and data share one atomic location, a reader that sees tag
+// t + 1 sees that step's bits; no cache writeback or invalidate is needed.
+// A workgroup first delivers its delay >= 2 synapses (history it already
+// holds), then waits for the tags of row t - 1 from every slice, then delivers
+// its delay-1 synapses.  A slice runs at most one step ahead of the slowest,
+// so a slot is never rewritten before every reader is done with it.  Without
+// an LDS ring the bits are read from the mailbox ring itself.  Every wait is
+// bounded: after kSpinLimit polls the workgroup records a timeout in *status
+// and all its waves exit; slices waiting on it then time out the same way.
 //
 // Thread tid owns the neurons of local groups wave + k * nwave (k < NPT), so
 // the ballot of a wave is the spike word of one group.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 22;
 
+__device__ __forceinline__ uint64_t load_dev(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_dev(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Delivers the chunks [c, c_end) of the calling wave's share (every nwave-th
+// chunk): four independent record / bit / accumulate chains per lane.
+template <bool RECS_LDS, bool RING_LDS>
+__device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const uint32_t* ring,
+                                        const uint64_t* mring, float* acc, int c, int c_end, int nwave,
+                                        int lane, int g0, int r0, int t, int cur, int Dr, int W32) {
+  for (; c < c_end; c += nwave) {
+    const uint2 ch = n.chunks[c];
+    const int start = static_cast<int>(ch.x);
+    const int lg = static_cast<int>(ch.y & 0xFFFFFu) - g0;
+    const int cnt = static_cast<int>(ch.y >> 20);
+    Rec rc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = lane + 64 * u;
+      rc[u] = Rec{0.f, 0u};
+      if (i < cnt) rc[u] = RECS_LDS ? lrec[start - r0 + i] : n.recs[start + i];
+    }
+    uint32_t bit[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t m = rc[u].meta;
+      const int d = static_cast<int>((m >> 20) & 63u) + 1;
+      const uint32_t pre = m & 0xFFFFFu;
+      bit[u] = 0u;
+      if (lane + 64 * u < cnt && t - d >= 0) {
+        int slot = cur - d;
+        if (slot < 0) slot += Dr;
+        const uint32_t word = RING_LDS ? ring[slot * W32 + (pre >> 5)]
+                                       : static_cast<uint32_t>(load_dev(mring + static_cast<size_t>(slot) * n.B * W32 + (pre >> 5)));
+        bit[u] = (word >> (pre & 31u)) & 1u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (bit[u]) atomicAdd(&acc[lg * kGroup + (rc[u].meta >> 26)], rc[u].w);
+    }
+  }
+}
+
+// One workgroup's share of a simulation: slice w, trial b, steps t0 ..
+// t0 + steps - 1.  Returns false when a wait timed out (every thread returns
+// the same value).
 template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI>
-__global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int abort_flag;
+__device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0, int steps, unsigned char* smem,
+                                         int& abort_flag) {
   const DevNet& n = a.n;
-  const int w = MULTI ? static_cast<int>(blockIdx.x) : 0;
-  const int b = MULTI ? static_cast<int>(blockIdx.y) : static_cast<int>(blockIdx.x);
   const int nthr = blockDim.x;
   const int nwave = nthr >> 6;
   const int tid = threadIdx.x;
@@ -82,18 +98,20 @@ __global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps
   const int W32 = 2 * n.G;
   const int g0 = a.wg_group[w];
   const int ng = a.wg_group[w + 1] - g0;
-  const int c0 = a.wg_chunk[w];
-  const int c1 = a.wg_chunk[w + 1];
+  const int cA0 = a.wg_chunk[w], cA1 = a.wg_chunk[w + 1];
+  const int cB0 = a.wg_chunk[a.P + 1 + w], cB1 = a.wg_chunk[a.P + 1 + w + 1];
   const int r0 = n.gptr[g0];
   const int nrec = n.gptr[g0 + ng] - r0;
+  const bool use_mail = MULTI || !RING_LDS;
+  // mailbox ring of this trial: slot s at mring + s * B * W32
+  uint64_t* mring = a.mailbox + static_cast<size_t>(b) * W32;
 
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);
   float* acc = reinterpret_cast<float*>(ring + (RING_LDS ? Dr * W32 : 0));
   Rec* lrec = reinterpret_cast<Rec*>(acc + a.ng_max * kGroup);  // offsets are multiples of 8 bytes
-  const size_t rstride = static_cast<size_t>(n.B) * n.G;
-  const uint64_t* hist = n.raster + static_cast<size_t>(b) * n.G;
 
   if (tid == 0) abort_flag = 0;
+  __syncthreads();
   if (RING_LDS) {
     for (int i = tid; i < Dr * W32; i += nthr) ring[i] = 0u;
   }
@@ -103,6 +121,8 @@ __global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps
   }
   __syncthreads();
   if (RING_LDS) {  // history of the steps before t0 (rows < 0 stay zero)
+    const size_t rstride = static_cast<size_t>(n.B) * n.G;
+    const uint64_t* hist = n.raster + static_cast<size_t>(b) * n.G;
     for (int d = 1; d <= n.D; ++d) {
       const int ts = t0 - d;
       if (ts < 0) break;
@@ -144,43 +164,31 @@ __global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps
       ew_next[k] = (lg < ng && t + 1 < t0 + steps) ? n.ext[row_word(n, t + 1, b, g0 + lg)] : 0ull;
     }
     const int cur = t % Dr;
-    // delivery: chunk c goes to wave (c - c0) mod nwave; a chunk holds at
-    // most kChunk = 4 * 64 records, processed as four independent
-    // record / bit / accumulate chains per lane
-    for (int c = c0 + wave; c < c1; c += nwave) {
-      const uint2 ch = n.chunks[c];
-      const int start = static_cast<int>(ch.x);
-      const int lg = static_cast<int>(ch.y & 0xFFFFFu) - g0;
-      const int cnt = static_cast<int>(ch.y >> 20);
-      Rec rc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = lane + 64 * u;
-        rc[u] = Rec{0.f, 0u};
-        if (i < cnt) rc[u] = RECS_LDS ? lrec[start - r0 + i] : n.recs[start + i];
-      }
-      uint32_t bit[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint32_t m = rc[u].meta;
-        const int d = static_cast<int>((m >> 20) & 63u) + 1;
-        const uint32_t pre = m & 0xFFFFFu;
-        bit[u] = 0u;
-        if (lane + 64 * u < cnt && t - d >= 0) {
-          if (RING_LDS) {
-            int slot = cur - d;
-            if (slot < 0) slot += Dr;
-            bit[u] = (ring[slot * W32 + (pre >> 5)] >> (pre & 31u)) & 1u;
-          } else {
-            bit[u] = static_cast<uint32_t>(hist[static_cast<size_t>(t - d) * rstride + (pre >> 6)] >> (pre & 63u)) & 1u;
+    // delay >= 2: every needed row is already held
+    deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, acc, cA0 + wave, cA1, nwave, lane, g0, r0, t, cur, Dr, W32);
+    if (MULTI && t > t0) {
+      // receive row t - 1 from every slice
+      const int prev = (t - 1) % Dr;
+      const uint64_t tag = static_cast<uint64_t>(t);
+      for (int i = tid; i < W32; i += nthr) {
+        const uint64_t* p = mring + static_cast<size_t>(prev) * n.B * W32 + i;
+        uint64_t v = load_dev(p);
+        uint32_t spins = 0;
+        while ((v >> 32) != tag) {
+          if (++spins > kSpinLimit) {
+            abort_flag = 1;
+            __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
           }
+          v = load_dev(p);
         }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (bit[u]) atomicAdd(&acc[lg * kGroup + (rc[u].meta >> 26)], rc[u].w);
+        if (RING_LDS) ring[prev * W32 + i] = static_cast<uint32_t>(v);
       }
     }
+    __syncthreads();
+    if (MULTI && abort_flag) return false;  // uniform: read after the barrier
+    // delay 1
+    deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, acc, cB0 + wave, cB1, nwave, lane, g0, r0, t, cur, Dr, W32);
     __syncthreads();
     // fused neuron update; the ballot of a wave is the spike word of its group
 #pragma unroll
@@ -191,41 +199,15 @@ __global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps
         acc[lg * kGroup + lane] = 0.f;
         const bool s = lif_update(V[k], ref[k], syn, (ew[k] >> lane) & 1ull, th[k], lam[k], rs[k], amp[k], R[k]);
         const uint64_t sw = __ballot(s);
-        if (lane == 0) {
-          const int g = g0 + lg;
-          n.raster[row_word(n, t, b, g)] = sw;
-          if (RING_LDS) {
-            ring[cur * W32 + 2 * g] = static_cast<uint32_t>(sw);
-            ring[cur * W32 + 2 * g + 1] = static_cast<uint32_t>(sw >> 32);
-          }
+        const int g = g0 + lg;
+        if (lane == 0) n.raster[row_word(n, t, b, g)] = sw;
+        if (RING_LDS && lane < 2) ring[cur * W32 + 2 * g + lane] = static_cast<uint32_t>(sw >> (32 * lane));
+        if (use_mail && lane < 2) {
+          const uint64_t tagged = (static_cast<uint64_t>(t + 1) << 32) | ((sw >> (32 * lane)) & 0xFFFFFFFFull);
+          store_dev(mring + static_cast<size_t>(cur) * n.B * W32 + 2 * g + lane, tagged);
         }
       }
       ew[k] = ew_next[k];
-    }
-    if (MULTI) {
-      __syncthreads();  // every spike word of this workgroup is written
-      uint32_t* flags = a.flags + static_cast<size_t>(b) * a.P;
-      if (tid == 0) __hip_atomic_store(&flags[w], static_cast<uint32_t>(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      for (int v = tid; v < a.P; v += nthr) {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&flags[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < static_cast<uint32_t>(t + 1)) {
-          if (++spins > kSpinLimit) {
-            abort_flag = 1;
-            __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-        }
-      }
-      __syncthreads();
-      if (abort_flag) return;  // uniform: every thread sees the flag after the barrier
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (RING_LDS) {
-        for (int i = tid; i < n.G; i += nthr) {
-          const uint64_t wv = hist[static_cast<size_t>(t) * rstride + i];
-          ring[cur * W32 + 2 * i] = static_cast<uint32_t>(wv);
-          ring[cur * W32 + 2 * i + 1] = static_cast<uint32_t>(wv >> 32);
-        }
-      }
     }
     __syncthreads();
   }
@@ -238,6 +220,105 @@ __global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps
       n.ref[static_cast<size_t>(b) * n.Npad + j] = static_cast<uint8_t>(ref[k]);
     }
   }
+  __syncthreads();  // the shared memory may be reused by the caller
+  return true;
+}
+
+template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI>
+__global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int abort_flag;
+  const int w = MULTI ? static_cast<int>(blockIdx.x) : 0;
+  const int b = MULTI ? static_cast<int>(blockIdx.y) : static_cast<int>(blockIdx.x);
+  sim_body<NPT, RECS_LDS, RING_LDS, MULTI>(a, w, b, t0, steps, smem, abort_flag);
+}
+
+// Mailbox before a launch starting at t0: slot of row r (t0 - D <= r < t0,
+// r >= 0) holds row r of the raster tagged r + 1; every other slot is zero
+// (tag 0 is never awaited), so no word left by an earlier launch can match a
+// tag this launch waits for.
+__global__ void k_prefill_mailbox(const SimArgs a, int t0) {
+  const DevNet& n = a.n;
+  const int W32 = 2 * n.G;
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int Dr = n.D + 1;
+  const size_t total = static_cast<size_t>(Dr) * n.B * W32;
+  if (i >= total) return;
+  const int word = static_cast<int>(i % W32);
+  const int b = static_cast<int>((i / W32) % n.B);
+  const int slot = static_cast<int>(i / (static_cast<size_t>(W32) * n.B));
+  // the row r in [t0 - D, t0] with r mod Dr == slot
+  int r = t0 - ((t0 - slot) % Dr + Dr) % Dr;
+  uint64_t v = 0;
+  if (r < t0 && r >= 0) {
+    const uint64_t wv = n.raster[row_word(n, r, b, word >> 1)];
+    v = (static_cast<uint64_t>(r + 1) << 32) | ((wv >> (32 * (word & 1))) & 0xFFFFFFFFull);
+  }
+  a.mailbox[i] = v;
+}
+
+hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
+  const size_t total = static_cast<size_t>(a.n.D + 1) * a.n.B * 2 * a.n.G;
+  hipLaunchKernelGGL(k_prefill_mailbox, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, a, t0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent kernel (see BatchArgs): workgroups 0 .. n_team - 1 first
+// run their team slice, then every workgroup takes queue entries until the
+// queue is empty.  Team slices wait only on slices of the same network, all
+// of which are resident (cooperative launch) and start with their team task.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs ba, int steps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int abort_flag;
+  __shared__ int next;
+  if (static_cast<int>(blockIdx.x) < ba.n_team) {
+    const int4 tt = ba.team[blockIdx.x];
+    const SimArgs a = ba.nets[tt.x].team;
+    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true>(a, tt.y, tt.z, tt.w, steps, smem,
+                                                                             abort_flag))
+      return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(ba.queue_head, 1);
+    __syncthreads();
+    const int i = next;
+    __syncthreads();
+    if (i >= ba.n_queue) return;
+    const int4 qt = ba.queue[i];
+    const SimArgs a = ba.nets[qt.x].single;
+    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false>(a, 0, qt.y, qt.z, steps, smem, abort_flag);
+  }
+}
+
+size_t batch_lds_bytes(const DevNet& n, int ng_max) {
+  return static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(ng_max) * kGroup * sizeof(float);
+}
+
+int batch_blocks_per_cu(size_t lds) {
+  int blocks = 0;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds)) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch, kBatchThreads, lds) != hipSuccess) return 0;
+  return blocks;
+}
+
+hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  void* args[] = {const_cast<BatchArgs*>(&a), &steps};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch), dim3(grid), dim3(kBatchThreads), args,
+                                    static_cast<unsigned>(lds), s);
+}
+
+__global__ void k_zero_i32(int32_t* p) { *p = 0; }
+
+hipError_t launch_zero_i32(int32_t* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, p);
+  return hipGetLastError();
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
@@ -300,20 +381,14 @@ hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0
   if (sim_npt(a.ng_max) > kMaxNpt) return hipErrorInvalidValue;
   const size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, recs_lds, ring_lds) - 64;
   if (lds + 64 > kLdsLimit) return hipErrorInvalidValue;
+  if (a.P > 1 || !ring_lds) {
+    const hipError_t e = launch_prefill_mailbox(a, t0, s);
+    if (e != hipSuccess) return e;
+  }
   if (a.P > 1) return launch_sim_m<true>(a, recs_lds, ring_lds, t0, steps, s, lds);
   return launch_sim_m<false>(a, recs_lds, ring_lds, t0, steps, s, lds);
 }
 
-__global__ void k_clear_u32(uint32_t* p, int count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0u;
-}
-
-hipError_t launch_clear_u32(uint32_t* p, int count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clear_u32, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // Per-step pull kernel: workgroup (g, b) accumulates, for trial b, the

@@ -35,15 +35,16 @@ constexpr int kChunk = 256;
 struct HostLayout {
   std::vector<Rec> recs;        // grouped by post-group, round-robin over posts inside a group
   std::vector<int32_t> gptr;    // [G + 1] record offset of every group
-  std::vector<uint2> chunks;    // chunk table (kChunk records max per chunk)
-  std::vector<int32_t> gchunk;  // [G + 1] first chunk of every group
+  std::vector<int32_t> gsplit;  // [G] first delay-1 record of every group
+  std::vector<uint2> chunks;    // chunk table: delay >= 2 chunks of all groups, then delay-1 chunks
+  std::vector<int32_t> gchunk;  // [2][G + 1] first chunk of every group, per part
   int32_t max_group_records = 0;
 };
 
 // Partition of the groups into P contiguous slices for the persistent kernel.
 struct SlicePlan {
   std::vector<int32_t> wg_group;  // [P + 1]
-  std::vector<int32_t> wg_chunk;  // [P + 1]
+  std::vector<int32_t> wg_chunk;  // [2][P + 1]: first delay>=2 chunk, then first delay-1 chunk, per slice
   int32_t P = 0;
   int32_t ng_max = 0;
   int64_t max_recs = 0;
@@ -90,13 +91,74 @@ struct DevNet {
 struct SimArgs {
   DevNet n;
   const int32_t* wg_group;  // [P + 1] first group of every slice
-  const int32_t* wg_chunk;  // [P + 1] first chunk of every slice
-  uint32_t* flags;          // [B][P] last step + 1 published by every slice
-  uint32_t* status;         // set to nonzero when a barrier wait times out
+  const int32_t* wg_chunk;  // [2][P + 1] first chunk of every slice: delay >= 2 part, delay-1 part
+  uint64_t* mailbox;        // [D + 1][B][2G] tagged spike words: (step + 1) << 32 | 32 spike bits
+  uint32_t* status;         // set to nonzero when a wait for a mailbox word times out
   int32_t P;
   int32_t ng_max;           // most groups in one slice
   int64_t max_recs;         // most records in one slice
 };
+
+// Dense delay-1 weights for the matrix-core path, bfloat16, tiled for
+// v_mfma_f32_16x16x32_bf16.  K (pre-neurons) is padded to kpad, a multiple
+// of 128, and walked in blocks j of 128 = 4 steps s x 4 lane groups q x 8:
+// at step (j, s) lane group q contracts pre-neurons 8 * (16 j + 4 q + s) + e,
+// e = 0..7, so one 32-bit word of a trial's spike bits feeds four steps.
+// Element (col tile c, j, s, q, col, e) = W[8 (16 j + 4 q + s) + e][16 c + col].
+struct DenseArgs {
+  DevNet n;
+  const uint16_t* wt;  // [Npad / 16][kpad / 128][4][4][16][8] bf16 bits
+  int32_t kpad;
+};
+
+size_t dense_tiled_elems(int32_t npad, int32_t kpad);
+void tile_dense_weights(const float* W, int32_t n, int32_t npad, int32_t kpad, uint16_t* out);
+
+// Event-driven ("push") delivery: out-going synapses of every neuron (CSR by
+// pre-neuron) and a ring of D + 1 accumulator rows; a spike of neuron i at t
+// adds w into row (t + d) mod (D+1) at the post-neuron.
+// Push record meta: bits 0..19 post-neuron, bits 20..25 delay - 1.
+struct PushArgs {
+  DevNet n;
+  const Rec* orecs;         // [nnz] out-going records grouped by pre-neuron
+  const int32_t* optr;      // [Npad + 1] first out-record of every neuron
+  const int32_t* wg_group;  // [P + 1] first group of every slice
+  float* accum;             // [D + 1][B][Npad] pending synaptic input
+  uint32_t* flags;          // [B][P][64] step + 1 finished by every slice (one flag per 256 bytes)
+  uint32_t* status;         // set to nonzero when a wait times out
+  int32_t P;
+  int32_t ng_max;
+};
+
+struct HostPush {
+  std::vector<Rec> orecs;
+  std::vector<int32_t> optr;  // [Npad + 1]
+};
+HostPush build_push_layout(int32_t n, int32_t npad, int64_t nnz, const int32_t* pre, const int32_t* post,
+                           const float* w, const uint8_t* delay);
+
+// Batched execution of independent networks in one persistent launch.
+// Networks too large for one workgroup run as a team of workgroups (their
+// slices, exchanging spikes through the network's mailbox); the others are
+// pulled one (network, trial) at a time from a work queue by whichever
+// workgroup is free.  Records are read from global memory (L2-resident for
+// small networks); the spike ring of every network lives in LDS.
+struct BatchNet {
+  SimArgs team;    // slice plan of a team network (P > 1)
+  SimArgs single;  // one-slice plan (P = 1)
+};
+
+struct BatchArgs {
+  const BatchNet* nets;
+  const int4* team;    // [n_team] (network, slice, trial, t0) of workgroups 0 .. n_team - 1
+  const int4* queue;   // [n_queue] (network, trial, t0, -) in the order they are taken
+  int32_t n_team;
+  int32_t n_queue;
+  int32_t* queue_head; // next queue entry to take (zero before the launch)
+};
+
+constexpr int kBatchThreads = 256;
+constexpr int kBatchMaxGroups = 32;  // groups per slice: 4 waves x 8 groups per wave
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, bool recs_lds, bool ring_lds);
@@ -104,8 +166,16 @@ size_t lds_limit();
 int sim_threads(int ng_max);
 int sim_npt(int ng_max);
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s);
-hipError_t launch_clear_u32(uint32_t* p, int count, hipStream_t s);
+hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s);
+size_t batch_lds_bytes(const DevNet& n, int ng_max);
+int batch_blocks_per_cu(size_t lds);
+hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
+hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
+hipError_t launch_dense_step(const DenseArgs& a, int32_t t, hipStream_t s);
+hipError_t launch_push(const PushArgs& a, int32_t t0, int32_t steps, hipStream_t s);
+hipError_t prepare_dense_kernel(int32_t kpad);
+size_t dense_lds_bytes(int32_t kpad);
 hipError_t launch_reset_state(const DevNet& n, hipStream_t s);
 hipError_t launch_repack_input(const DevNet& n, int32_t t0, int32_t steps, const uint32_t* bits,
                                hipStream_t s);

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import check
 
 PATHS = {"auto": _lib.PATH_AUTO, "small": _lib.PATH_SMALL, "step": _lib.PATH_STEP,
-         "persist": _lib.PATH_PERSIST, "dense": _lib.PATH_DENSE}
+         "persist": _lib.PATH_PERSIST, "dense": _lib.PATH_DENSE, "push": _lib.PATH_PUSH}
 
 
 class TorchAllocator:
@@ -174,6 +174,36 @@ class Network:
     def close(self):
         if getattr(self, "h", None):
             self.lib.sn_destroy_network(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent networks advanced together by one persistent launch."""
+
+    def __init__(self, networks):
+        self.networks = list(networks)  # keeps the networks (and their allocators) alive
+        self.lib = _lib.load()
+        arr = (ctypes.c_void_p * len(self.networks))(*[g.h.value for g in self.networks])
+        handle = ctypes.c_void_p()
+        check(self.lib.sn_batch_create(arr, len(self.networks), ctypes.byref(handle)))
+        self.h = handle
+
+    def run(self, steps: int):
+        check(self.lib.sn_batch_run(self.h, int(steps)))
+
+    def synchronize(self):
+        if self.networks:
+            self.networks[0].synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sn_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

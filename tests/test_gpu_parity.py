@@ -51,7 +51,7 @@ def assert_parity(net, res, spikes, V, ref, what=""):
     assert np.array_equal(ref.astype(np.int32), res.ref), f"{net.name} {what}: refractory counters differ"
 
 
-PATHS = ["small", "step", "persist"]
+PATHS = ["small", "step", "persist", "push"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -86,7 +86,7 @@ def test_mixed_paths_and_reset(gpu, oracle):
     net = wl.random_small(78, n=70, p=0.3, max_delay=5, steps=80, hetero=True)
     res = oracle.run_sparse(net)
     g = gpu.from_workload(net)
-    for path, c in [("small", 13), ("step", 20), ("persist", 9), ("small", 31), ("step", 7)]:
+    for path, c in [("small", 13), ("step", 20), ("persist", 9), ("push", 5), ("small", 14), ("push", 12), ("step", 7)]:
         g.set_path(path)
         g.run(c)
     assert_parity(net, res, g.read_raster(0, 80), *g.read_state(), "mixed")
@@ -120,18 +120,29 @@ def test_persist_slices(gpu, oracle, slices):
 
 def test_persist_global_ring(gpu, oracle):
     """A spike ring too large for LDS (N = 40,000, D = 64): bits come from the
-    raster in global memory."""
+    tagged mailbox ring in global memory.  A request for one slice is raised
+    to the five slices 625 groups need."""
     net = wl.large_sparse(13, n=40_000, p=0.0005, steps=120, max_delay=64)
     res = oracle.run_sparse(net)
-    for path in ("persist", "step"):
-        s, V, r, used = simulate(gpu, net, path)
-        assert_parity(net, res, s, V, r, path)
+    for path, slices in (("persist", 0), ("persist", 4), ("persist", 1), ("step", 0)):
+        s, V, r, used = simulate(gpu, net, path, chunks=[50, 70], slices=slices)
+        assert_parity(net, res, s, V, r, f"{path} slices={slices}")
 
 
 def test_large_sparse_low_rate(gpu, oracle):
     net = wl.large_sparse_low(2, steps=300)
     res = oracle.run_sparse(net)
-    s, V, r, used = simulate(gpu, net, "auto")
+    for path in ("auto", "push", "persist"):
+        s, V, r, used = simulate(gpu, net, path, chunks=[100, 200])
+        assert_parity(net, res, s, V, r, used)
+
+
+def test_push_large_sparse(gpu, oracle):
+    """Event-driven delivery on the benchmarked net (high rate: every
+    accumulator row receives many atomics per step)."""
+    net = wl.large_sparse(2, steps=400)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "push", chunks=[150, 250])
     assert_parity(net, res, s, V, r, used)
 
 
@@ -205,3 +216,74 @@ def test_error_paths(gpu):
         W[0, 1] = 1.0 + 2.0 ** -10                   # not a bfloat16 value
         g.load_dense_weights(W)
     g.close()
+
+
+def test_dense_trials_small(gpu, oracle):
+    """Dense weights on the matrix cores: several trials, ragged N and B."""
+    for (n, trials, seed) in [(100, 3, 31), (256, 17, 32), (130, 64, 33), (64, 70, 34)]:
+        net = wl.dense_trials(seed, n=n, trials=trials, steps=60, drive_p=0.05)
+        res = oracle.run_dense(net)
+        for path in ("dense", "step", "persist", "push"):
+            s, V, r, used = simulate(gpu, net, path)
+            assert used == path
+            assert_parity(net, res, s, V, r, f"{path} n={n} trials={trials}")
+
+
+def test_dense_trials_full_sampled(gpu, oracle):
+    """The benchmarked dense workload (N = 4096, 64 trials, T = 1000) in the
+    benchmark's launch configuration; the oracle checks three trials."""
+    net = wl.dense_trials(3)
+    g = gpu.from_workload(net)
+    g.run(net.steps)
+    assert g.progress[1] == "dense"
+    spikes = g.read_raster(0, net.steps)
+    V, ref = g.read_state()
+    g.close()
+    picks = [0, 37, 63]
+    res = oracle.run_dense(net, trials=picks)
+    assert res.exact
+    assert np.array_equal(spikes[picks], res.spikes)
+    assert np.array_equal(V[picks].astype(np.float64), res.V)
+    assert np.array_equal(ref[picks].astype(np.int32), res.ref)
+    # every trial obeys refractoriness and the firing stays in the expected regime
+    from oracle_pins import check_refractory
+    check_refractory(spikes[:, :300], net.refractory)
+    assert 0.001 < spikes.mean() < 0.2
+
+
+def test_batch_uneven(gpu, oracle):
+    """Uneven batch of independent nets in one persistent launch: every net
+    bit-exact against its own oracle run, resumed over two batch runs."""
+    from paper_2305_02510_amd import Batch
+    nets = wl.uneven_batch(4, count=40, steps=120, n_range=(50, 3000), p_range=(0.005, 0.1))
+    gs = [gpu.from_workload(net) for net in nets]
+    batch = Batch(gs)
+    batch.run(50)
+    batch.run(70)
+    batch.synchronize()
+    for net, g in zip(nets, gs):
+        assert g.progress == (120, "batch")
+        res = oracle.run_sparse(net)
+        assert_parity(net, res, g.read_raster(0, net.steps), *g.read_state(), "batch")
+    batch.close()
+    for g in gs:
+        g.close()
+
+
+def test_batch_with_trials_and_mixed_paths(gpu, oracle):
+    """Nets with several trials, and a batch run following single-net runs."""
+    from paper_2305_02510_amd import Batch
+    nets = [wl.random_small(2000 + i, n=[30, 200, 700][i % 3], p=0.1, max_delay=1 + i % 5, steps=90,
+                            trials=1 + i % 3, hetero=True) for i in range(9)]
+    nets.append(wl.large_sparse(21, n=6000, p=0.01, steps=90))
+    gs = [gpu.from_workload(net) for net in nets]
+    for g in gs:
+        g.run(30)
+    batch = Batch(gs)
+    batch.run(60)
+    for net, g in zip(nets, gs):
+        res = oracle.run_sparse(net)
+        assert_parity(net, res, g.read_raster(0, net.steps), *g.read_state(), "batch after run")
+    batch.close()
+    for g in gs:
+        g.close()
