@@ -41,6 +41,9 @@ def _bind(lib):
     lib.or_lif_sparse.restype = ctypes.c_int
     lib.or_lif_sparse.argtypes = [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
                                   _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int]
+    lib.or_bptt.restype = ctypes.c_int
+    lib.or_bptt.argtypes = [_I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
     lib.or_lif_dense.restype = ctypes.c_int
     lib.or_lif_dense.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P, _P, ctypes.c_int]
@@ -113,6 +116,37 @@ class Oracle:
             raise ValueError(f"oracle rejected the input (status {rc})")
         return OracleResult(spikes, V, ref, rc == OR_OK)
 
+
+@dataclasses.dataclass
+class BpttResult:
+    loss: float
+    dW_rec: np.ndarray   # float64 [N][N]
+    dW_in: np.ndarray    # float64 [Nin][N]
+    counts: np.ndarray   # float64 [B][N] spike counts
+
+
+def _bptt(self, W_rec, W_in, x, target, theta=1.0, leak=0.0625, reset=0.0, slope=10.0, relaxed=False):
+    """Surrogate-gradient BPTT of the recurrent LIF layer (see or_bptt).
+    x: uint8 [T][B][Nin] input spikes."""
+    W_rec = np.ascontiguousarray(W_rec, np.float64)
+    W_in = np.ascontiguousarray(W_in, np.float64)
+    x = np.ascontiguousarray(x, np.uint8)
+    target = np.ascontiguousarray(target, np.float64)
+    T, B, Nin = x.shape
+    N = W_rec.shape[0]
+    dWr = np.zeros((N, N))
+    dWi = np.zeros((Nin, N))
+    counts = np.zeros((B, N))
+    loss = ctypes.c_double()
+    P = self._ptr
+    rc = self.lib.or_bptt(N, Nin, B, T, theta, leak, reset, slope, int(relaxed), P(W_rec), P(W_in), P(x),
+                          P(target), ctypes.cast(ctypes.byref(loss), ctypes.c_void_p), P(dWr), P(dWi), P(counts))
+    if rc != OR_OK:
+        raise ValueError(f"oracle rejected the input (status {rc})")
+    return BpttResult(loss.value, dWr, dWi, counts)
+
+
+Oracle.bptt = _bptt
 
 _default: Optional[Oracle] = None
 

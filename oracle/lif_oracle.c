@@ -223,3 +223,121 @@ int or_lif_dense(int32_t N, int32_t B, int32_t T,
     free(U);
     return exact ? OR_OK : OR_NONEXACT;
 }
+
+/*
+ * Surrogate-gradient backpropagation through time for a recurrent LIF layer
+ * (the model above with delay-1 recurrent weights W_rec [N][N], external
+ * input through W_in [Nin][N], no refractory period):
+ *   U_t = leak(V_{t-1}) + s_{t-1} W_rec + x_t W_in
+ *   s_t = H(U_t - theta)           (relaxed: s~(U_t - theta), see below)
+ *   V_t = (1 - s_t) U_t + s_t r
+ * Loss: L = mean over (b, j) of (c_bj / T - target_j)^2 with c_bj = sum_t s_t.
+ * Threshold derivative ("fast sigmoid" surrogate of slope k):
+ *   ds/dU := (k/2) / (1 + k |U - theta|)^2,
+ * which is the exact derivative of s~(x) = 1/2 + (k/2) x / (1 + k|x|), a
+ * sigmoid with range (0, 1).  relaxed != 0 runs the forward with s~ instead
+ * of H, so the returned gradient is then the true gradient of that forward.
+ * The leak is differentiated as 1 where it is not clamped (|V - r| > lambda),
+ * 0 where it is.  Gradients are accumulated into dW_rec, dW_in (zeroed here).
+ */
+static double surrogate(double x, double k) {
+    double d = 1.0 + k * fabs(x);
+    return 0.5 * k / (d * d);
+}
+
+static double relaxed_spike(double x, double k) {
+    return 0.5 + 0.5 * k * x / (1.0 + k * fabs(x));
+}
+
+int or_bptt(int32_t N, int32_t Nin, int32_t B, int32_t T, double theta, double lambda, double r,
+            double k, int relaxed, const double* W_rec, const double* W_in, const uint8_t* x,
+            const double* target, double* loss, double* dW_rec, double* dW_in, double* counts) {
+    if (N < 1 || Nin < 0 || B < 1 || T < 1) return OR_EINVAL;
+    size_t S = (size_t)T * B * N;
+    double* U = (double*)malloc(S * sizeof(double));
+    double* s = (double*)malloc(S * sizeof(double));
+    double* V = (double*)malloc(S * sizeof(double));
+    double* gU = (double*)calloc((size_t)B * N, sizeof(double));
+    double* gUn = (double*)malloc((size_t)B * N * sizeof(double));
+    if (!U || !s || !V || !gU || !gUn) {
+        free(U); free(s); free(V); free(gU); free(gUn);
+        return OR_ENOMEM;
+    }
+    /* forward */
+    for (int32_t t = 0; t < T; ++t) {
+        for (int32_t b = 0; b < B; ++b) {
+            double* Ut = U + ((size_t)t * B + b) * N;
+            for (int32_t j = 0; j < N; ++j)
+                Ut[j] = apply_leak(t > 0 ? V[((size_t)(t - 1) * B + b) * N + j] : r, r, lambda);
+            if (t > 0) {
+                const double* sp = s + ((size_t)(t - 1) * B + b) * N;
+                for (int32_t i = 0; i < N; ++i) {
+                    if (sp[i] == 0.0) continue;
+                    for (int32_t j = 0; j < N; ++j) Ut[j] += sp[i] * W_rec[(size_t)i * N + j];
+                }
+            }
+            const uint8_t* xt = x + ((size_t)t * B + b) * Nin;
+            for (int32_t i = 0; i < Nin; ++i) {
+                if (!xt[i]) continue;
+                for (int32_t j = 0; j < N; ++j) Ut[j] += W_in[(size_t)i * N + j];
+            }
+            double* st = s + ((size_t)t * B + b) * N;
+            double* Vt = V + ((size_t)t * B + b) * N;
+            for (int32_t j = 0; j < N; ++j) {
+                st[j] = relaxed ? relaxed_spike(Ut[j] - theta, k) : (Ut[j] > theta ? 1.0 : 0.0);
+                Vt[j] = (1.0 - st[j]) * Ut[j] + st[j] * r;
+            }
+        }
+    }
+    /* loss and its derivative with respect to every s_t (the same for all t) */
+    double L = 0.0;
+    for (int32_t b = 0; b < B; ++b)
+        for (int32_t j = 0; j < N; ++j) {
+            double c = 0.0;
+            for (int32_t t = 0; t < T; ++t) c += s[((size_t)t * B + b) * N + j];
+            counts[(size_t)b * N + j] = c;
+            double e = c / T - target[j];
+            L += e * e;
+        }
+    *loss = L / ((double)B * N);
+    for (size_t q = 0; q < (size_t)N * N; ++q) dW_rec[q] = 0.0;
+    for (size_t q = 0; q < (size_t)Nin * N; ++q) dW_in[q] = 0.0;
+    /* backward: gU holds dL/dU_{t+1} (zero beyond the last step) */
+    for (int32_t t = T - 1; t >= 0; --t) {
+        for (int32_t b = 0; b < B; ++b) {
+            const double* Ut = U + ((size_t)t * B + b) * N;
+            const double* st = s + ((size_t)t * B + b) * N;
+            const double* Vt = V + ((size_t)t * B + b) * N;
+            const double* gnext = gU + (size_t)b * N;
+            double* gcur = gUn + (size_t)b * N;
+            for (int32_t i = 0; i < N; ++i) {
+                /* dL/ds_t: through the loss and through s_t W_rec into U_{t+1} */
+                double a = 2.0 * (counts[(size_t)b * N + i] / T - target[i]) / ((double)B * N * T);
+                for (int32_t j = 0; j < N; ++j) a += gnext[j] * W_rec[(size_t)i * N + j];
+                /* dL/dV_t: through leak(V_t) into U_{t+1} */
+                double gv = fabs(Vt[i] - r) > lambda ? gnext[i] : 0.0;
+                double sg = surrogate(Ut[i] - theta, k);
+                gcur[i] = a * sg + gv * ((1.0 - st[i]) + (r - Ut[i]) * sg);
+            }
+        }
+        /* weight gradients: U_t = ... + s_{t-1} W_rec + x_t W_in */
+        for (int32_t b = 0; b < B; ++b) {
+            const double* gcur = gUn + (size_t)b * N;
+            if (t > 0) {
+                const double* sp = s + ((size_t)(t - 1) * B + b) * N;
+                for (int32_t i = 0; i < N; ++i) {
+                    if (sp[i] == 0.0) continue;
+                    for (int32_t j = 0; j < N; ++j) dW_rec[(size_t)i * N + j] += sp[i] * gcur[j];
+                }
+            }
+            const uint8_t* xt = x + ((size_t)t * B + b) * Nin;
+            for (int32_t i = 0; i < Nin; ++i) {
+                if (!xt[i]) continue;
+                for (int32_t j = 0; j < N; ++j) dW_in[(size_t)i * N + j] += gcur[j];
+            }
+        }
+        double* tmp = gU; gU = gUn; gUn = tmp;
+    }
+    free(U); free(s); free(V); free(gU); free(gUn);
+    return OR_OK;
+}

@@ -77,6 +77,7 @@ struct sn_net {
   const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t slices_req = 0;
   uint64_t* mailbox = nullptr;  // [D + 1][B][2G] tagged spike words
+  uint32_t* slice_flags = nullptr;  // [B][256][64]
   uint32_t* status = nullptr;
   HostLayout layout;          // kept to re-plan when the slice count changes
 };
@@ -156,8 +157,12 @@ sn_status ensure_rows(sn_net* n, int64_t rows) {
 // false if the slice plan cannot run at all.
 bool fit_plan(const DevNet& d, SlicePlan& p) {
   if (p.P < 1 || sim_npt(p.ng_max) > 8) return false;
+  // the spike ring goes to LDS whenever it fits beside the accumulators: a
+  // global ring costs a device-scope load per synapse
+  const bool ring_fits = sim_lds_bytes(d, p.ng_max, 0, false, true) <= 96 * 1024;
   const bool opts[4][2] = {{true, true}, {true, false}, {false, true}, {false, false}};
   for (const auto& o : opts) {
+    if (ring_fits && !o[1]) continue;
     if (sim_lds_bytes(d, p.ng_max, p.max_recs, o[0], o[1]) <= lds_limit()) {
       p.recs_lds = o[0];
       p.ring_lds = o[1];
@@ -224,6 +229,7 @@ SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
   a.wg_group = static_cast<const int32_t*>(dp.wg);
   a.wg_chunk = static_cast<const int32_t*>(dp.wg) + dp.host.P + 1;
   a.mailbox = n->mailbox;
+  a.flags = n->slice_flags;
   a.status = n->status;
   a.P = dp.host.P;
   a.ng_max = dp.host.ng_max;
@@ -426,6 +432,7 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
       int32_t p = std::max<int32_t>((G + kBatchMaxGroups - 1) / kBatchMaxGroups,
                                     static_cast<int32_t>(std::ceil(cost[k] / target)));
       p = std::min(p, G);
+      p = std::min(p, std::max(1, kMaxCoopGroups / v[k]->d.B));  // slice flags hold 256 slices per trial
       P[k] = p;
       if (p > 1) team_wgs += static_cast<int64_t>(p) * v[k]->d.B;
     }
@@ -523,6 +530,7 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
     a.wg_group = tables + bt->plan_off[k];
     a.wg_chunk = tables + bt->plan_off[k] + p.P + 1;
     a.mailbox = n->mailbox;
+    a.flags = n->slice_flags;
     a.status = n->status;
     a.P = p.P;
     a.ng_max = p.ng_max;
@@ -629,11 +637,13 @@ sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc, 
   n->d.V = static_cast<float*>(V);
   n->d.ref = static_cast<uint8_t*>(R);
   const size_t mail_bytes = static_cast<size_t>(D + 1) * B * 2 * G * sizeof(uint64_t);
-  void* F = dev_alloc(n, mail_bytes + 256);
+  const size_t flag_bytes = static_cast<size_t>(std::min(B, kMaxCoopGroups)) * kMaxCoopGroups * 64 * sizeof(uint32_t);
+  void* F = dev_alloc(n, mail_bytes + flag_bytes + 256);
   if (F) n->owned.push_back(F);
   n->mailbox = static_cast<uint64_t*>(F);
-  n->status = F ? reinterpret_cast<uint32_t*>(static_cast<char*>(F) + mail_bytes) : nullptr;
-  if (F && hipMemsetAsync(F, 0, mail_bytes + 256, n->stream) != hipSuccess) F = nullptr;
+  n->slice_flags = F ? reinterpret_cast<uint32_t*>(static_cast<char*>(F) + mail_bytes) : nullptr;
+  n->status = F ? reinterpret_cast<uint32_t*>(static_cast<char*>(F) + mail_bytes + flag_bytes) : nullptr;
+  if (F && hipMemsetAsync(F, 0, mail_bytes + flag_bytes + 256, n->stream) != hipSuccess) F = nullptr;
   if (!n->d.theta || !n->d.leak || !n->d.reset || !n->d.amp || !n->d.refr || !V || !R || !F) {
     sn_destroy_network(n);
     return fail(SN_ENOMEM, "cannot allocate or upload neuron arrays");

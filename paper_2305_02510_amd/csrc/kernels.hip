@@ -2,6 +2,8 @@
 // leak / integrate / threshold / refractory / reset update of §2.1.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sn_device.h"
 #include "sn_internal.h"
 
@@ -43,23 +45,36 @@ __device__ __forceinline__ void store_dev(uint64_t* p, uint64_t v) {
 }
 
 // Delivers the chunks [c, c_end) of the calling wave's share (every nwave-th
-// chunk): four independent record / bit / accumulate chains per lane.
+// chunk): four independent record / bit / accumulate chains per lane.  When
+// records stream from global memory, the next chunk's records are loaded
+// while the current one is processed.
+template <bool RECS_LDS>
+__device__ __forceinline__ void load_chunk(const DevNet& n, const Rec* lrec, int c, int lane, int r0, Rec (&rc)[4],
+                                           int& lg_g, int& cnt) {
+  const uint2 ch = n.chunks[c];
+  const int start = static_cast<int>(ch.x);
+  lg_g = static_cast<int>(ch.y & 0xFFFFFu);
+  cnt = static_cast<int>(ch.y >> 20);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = lane + 64 * u;
+    rc[u] = Rec{0.f, 0u};
+    if (i < cnt) rc[u] = RECS_LDS ? lrec[start - r0 + i] : n.recs[start + i];
+  }
+}
+
 template <bool RECS_LDS, bool RING_LDS>
 __device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const uint32_t* ring,
                                         const uint64_t* mring, float* acc, int c, int c_end, int nwave,
                                         int lane, int g0, int r0, int t, int cur, int Dr, int W32) {
+  if (c >= c_end) return;
+  Rec rc[4];
+  int g = 0, cnt = 0;
+  load_chunk<RECS_LDS>(n, lrec, c, lane, r0, rc, g, cnt);
   for (; c < c_end; c += nwave) {
-    const uint2 ch = n.chunks[c];
-    const int start = static_cast<int>(ch.x);
-    const int lg = static_cast<int>(ch.y & 0xFFFFFu) - g0;
-    const int cnt = static_cast<int>(ch.y >> 20);
-    Rec rc[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = lane + 64 * u;
-      rc[u] = Rec{0.f, 0u};
-      if (i < cnt) rc[u] = RECS_LDS ? lrec[start - r0 + i] : n.recs[start + i];
-    }
+    Rec nx[4];
+    int ng = 0, ncnt = 0;
+    if (!RECS_LDS && c + nwave < c_end) load_chunk<RECS_LDS>(n, lrec, c + nwave, lane, r0, nx, ng, ncnt);
     uint32_t bit[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -75,16 +90,24 @@ __device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const 
         bit[u] = (word >> (pre & 31u)) & 1u;
       }
     }
+    const int lg = g - g0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (bit[u]) atomicAdd(&acc[lg * kGroup + (rc[u].meta >> 26)], rc[u].w);
     }
+    if (c + nwave < c_end) {
+      if (RECS_LDS) {
+        load_chunk<RECS_LDS>(n, lrec, c + nwave, lane, r0, rc, g, cnt);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rc[u] = nx[u];
+        g = ng;
+        cnt = ncnt;
+      }
+    }
   }
 }
 
-// One workgroup's share of a simulation: slice w, trial b, steps t0 ..
-// t0 + steps - 1.  Returns false when a wait timed out (every thread returns
-// the same value).
 template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI>
 __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0, int steps, unsigned char* smem,
                                          int& abort_flag) {
@@ -167,7 +190,22 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     // delay >= 2: every needed row is already held
     deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, acc, cA0 + wave, cA1, nwave, lane, g0, r0, t, cur, Dr, W32);
     if (MULTI && t > t0) {
-      // receive row t - 1 from every slice
+      // receive row t - 1: wait until every slice has published step t - 1
+      // (one padded flag per slice), then read the row's tagged words; a tag
+      // is checked on every word and a word not yet visible is waited for
+      const uint32_t* flags = a.flags + static_cast<size_t>(b) * a.P * 64;
+      for (int v = tid; v < a.P; v += nthr) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&flags[v * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < static_cast<uint32_t>(t)) {
+          if (++spins > kSpinLimit) {
+            abort_flag = 1;
+            __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      if (abort_flag) return false;  // uniform: read after the barrier
       const int prev = (t - 1) % Dr;
       const uint64_t tag = static_cast<uint64_t>(t);
       for (int i = tid; i < W32; i += nthr) {
@@ -209,6 +247,14 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
       }
       ew[k] = ew_next[k];
     }
+    if (MULTI) {
+      // publish step t once every mailbox word of this slice is written
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_store(&a.flags[(static_cast<size_t>(b) * a.P + w) * 64], static_cast<uint32_t>(t + 1),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -243,7 +289,10 @@ __global__ void k_prefill_mailbox(const SimArgs a, int t0) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int Dr = n.D + 1;
   const size_t total = static_cast<size_t>(Dr) * n.B * W32;
-  if (i >= total) return;
+  if (i >= total) {
+    if (a.P > 1 && i < static_cast<size_t>(n.B) * a.P * 64) a.flags[i] = 0u;
+    return;
+  }
   const int word = static_cast<int>(i % W32);
   const int b = static_cast<int>((i / W32) % n.B);
   const int slot = static_cast<int>(i / (static_cast<size_t>(W32) * n.B));
@@ -255,10 +304,11 @@ __global__ void k_prefill_mailbox(const SimArgs a, int t0) {
     v = (static_cast<uint64_t>(r + 1) << 32) | ((wv >> (32 * (word & 1))) & 0xFFFFFFFFull);
   }
   a.mailbox[i] = v;
+  if (a.P > 1 && i < static_cast<size_t>(n.B) * a.P * 64) a.flags[i] = 0u;  // no flag of an earlier launch survives
 }
 
 hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
-  const size_t total = static_cast<size_t>(a.n.D + 1) * a.n.B * 2 * a.n.G;
+  const size_t total = std::max(static_cast<size_t>(a.n.D + 1) * a.n.B * 2 * a.n.G, static_cast<size_t>(a.n.B) * a.P * 64);
   hipLaunchKernelGGL(k_prefill_mailbox, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, a, t0);
   return hipGetLastError();
 }

@@ -93,7 +93,8 @@ struct SimArgs {
   const int32_t* wg_group;  // [P + 1] first group of every slice
   const int32_t* wg_chunk;  // [2][P + 1] first chunk of every slice: delay >= 2 part, delay-1 part
   uint64_t* mailbox;        // [D + 1][B][2G] tagged spike words: (step + 1) << 32 | 32 spike bits
-  uint32_t* status;         // set to nonzero when a wait for a mailbox word times out
+  uint32_t* flags;          // [B][P][64] step + 1 published by every slice (one flag per 256 bytes)
+  uint32_t* status;         // set to nonzero when a wait times out
   int32_t P;
   int32_t ng_max;           // most groups in one slice
   int64_t max_recs;         // most records in one slice
@@ -158,7 +159,7 @@ struct BatchArgs {
 };
 
 constexpr int kBatchThreads = 256;
-constexpr int kBatchMaxGroups = 32;  // groups per slice: 4 waves x 8 groups per wave
+constexpr int kBatchMaxGroups = 16;  // groups per slice: 4 waves x 4 groups per wave
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, bool recs_lds, bool ring_lds);
