@@ -215,6 +215,49 @@ sn_status sn_batch_run(sn_batch* batch, int32_t n_steps);
 /* Frees the batch (not its networks).  NULL is ignored. */
 void sn_batch_destroy(sn_batch* batch);
 
+/* ---- Surrogate-gradient training of a recurrent LIF layer --------------
+ * The layer is the model above with delay-1 recurrent weights W_rec
+ * [N][N], an external input x_t [B][Nin] entering through W_in [Nin][N],
+ * one threshold / leak / reset for all neurons and no refractory period:
+ *   U_t = leak(V_{t-1}) + s_{t-1} W_rec + x_t W_in,  s_t = (U_t > theta),
+ *   V_t = (1 - s_t) U_t + s_t r,   count = sum over t of s_t.
+ * Weights are passed stacked as W_cat [N + Nin][N] (rows 0..N-1: W_rec).
+ * The backward pass replaces the threshold's derivative by the fast-sigmoid
+ * surrogate 1 / (1 + k |U - theta|)^2 (k = slope), which is the exact
+ * derivative of the relaxed spike 1/2 + x / (1 + k|x|), x = U - theta; with
+ * relaxed != 0 the forward itself uses the relaxed spike, so the gradient is
+ * then the exact gradient of that forward.
+ * The clamped leak passes gradient only where it does not clamp.  Spikes are
+ * kept bit-packed (relaxed: as floats) and V every checkpoint_every steps;
+ * the backward pass recomputes each segment from its checkpoint.
+ * All arrays are device memory in binary32, row-major; work is issued on
+ * hip_stream (NULL: the null stream). */
+typedef struct {
+  int32_t n_neurons;         /* N, a multiple of 32 */
+  int32_t n_inputs;          /* Nin >= 0 */
+  int32_t n_trials;          /* B >= 1 */
+  int32_t n_steps;           /* T >= 1 */
+  int32_t checkpoint_every;  /* K >= 1 */
+  float threshold, leak, reset, slope;
+  int32_t relaxed;
+} sn_bptt_desc;
+
+/* Bytes of device workspace sn_bptt_forward / sn_bptt_backward need (0 if
+ * the descriptor is invalid). */
+size_t sn_bptt_workspace_bytes(const sn_bptt_desc* d);
+
+/* Forward pass: x [T][B][Nin] (spikes as 0/1 or any real input) -> spike
+ * counts [B][N]; fills the workspace for the backward pass.
+ * Errors: SN_EINVAL (null pointer, bad descriptor), SN_EDEVICE. */
+sn_status sn_bptt_forward(const sn_bptt_desc* d, const float* W_cat, const float* x, float* counts,
+                          void* workspace, void* hip_stream);
+
+/* Backward pass after sn_bptt_forward with the same inputs and workspace:
+ * given dL/dcounts [B][N], writes dL/dW_cat [N + Nin][N].
+ * Errors: SN_EINVAL, SN_EDEVICE. */
+sn_status sn_bptt_backward(const sn_bptt_desc* d, const float* W_cat, const float* x, const float* dcounts,
+                           const void* workspace, float* dW_cat, void* hip_stream);
+
 /* Frees the network and its device memory after its work has finished.
  * NULL is ignored. */
 void sn_destroy_network(sn_net* net);

@@ -232,21 +232,22 @@ int or_lif_dense(int32_t N, int32_t B, int32_t T,
  *   s_t = H(U_t - theta)           (relaxed: s~(U_t - theta), see below)
  *   V_t = (1 - s_t) U_t + s_t r
  * Loss: L = mean over (b, j) of (c_bj / T - target_j)^2 with c_bj = sum_t s_t.
- * Threshold derivative ("fast sigmoid" surrogate of slope k):
- *   ds/dU := (k/2) / (1 + k |U - theta|)^2,
- * which is the exact derivative of s~(x) = 1/2 + (k/2) x / (1 + k|x|), a
- * sigmoid with range (0, 1).  relaxed != 0 runs the forward with s~ instead
- * of H, so the returned gradient is then the true gradient of that forward.
+ * Threshold derivative (the "fast sigmoid" surrogate of slope k):
+ *   ds/dU := 1 / (1 + k |U - theta|)^2,
+ * which is the exact derivative of s~(x) = 1/2 + x / (1 + k|x|), a sigmoid
+ * step of range (1/2 - 1/k, 1/2 + 1/k).  relaxed != 0 runs the forward with
+ * s~ instead of H, so the returned gradient is then the true gradient of
+ * that forward.
  * The leak is differentiated as 1 where it is not clamped (|V - r| > lambda),
  * 0 where it is.  Gradients are accumulated into dW_rec, dW_in (zeroed here).
  */
 static double surrogate(double x, double k) {
     double d = 1.0 + k * fabs(x);
-    return 0.5 * k / (d * d);
+    return 1.0 / (d * d);
 }
 
 static double relaxed_spike(double x, double k) {
-    return 0.5 + 0.5 * k * x / (1.0 + k * fabs(x));
+    return 0.5 + x / (1.0 + k * fabs(x));
 }
 
 int or_bptt(int32_t N, int32_t Nin, int32_t B, int32_t T, double theta, double lambda, double r,

@@ -19,6 +19,7 @@ EXPORTS = [
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_get_progress", "sn_destroy_network", "sn_last_error",
     "sn_batch_create", "sn_batch_run", "sn_batch_destroy",
+    "sn_bptt_workspace_bytes", "sn_bptt_forward", "sn_bptt_backward",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -568,6 +568,32 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
   return SN_OK;
 }
 
+static bool bptt_desc_ok(const sn_bptt_desc* d) {
+  return d && d->n_neurons >= 32 && d->n_neurons % 32 == 0 && d->n_inputs >= 0 && d->n_trials >= 1 && d->n_steps >= 1 &&
+         d->checkpoint_every >= 1 && std::isfinite(d->threshold) && d->leak >= 0.f && std::isfinite(d->leak) &&
+         std::isfinite(d->reset) && std::isfinite(d->slope) && d->slope > 0.f;
+}
+
+size_t sn_bptt_workspace_bytes(const sn_bptt_desc* d) { return bptt_desc_ok(d) ? bptt_workspace_bytes(*d) : 0; }
+
+sn_status sn_bptt_forward(const sn_bptt_desc* d, const float* W_cat, const float* x, float* counts, void* workspace,
+                          void* hip_stream) {
+  if (!bptt_desc_ok(d)) return fail(SN_EINVAL, "invalid BPTT descriptor (N must be a positive multiple of 32)");
+  if (!W_cat || !x || !counts || !workspace) return fail(SN_EINVAL, "null pointer");
+  const hipError_t e = bptt_forward(*d, W_cat, x, counts, workspace, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(SN_EDEVICE, "BPTT forward: %s", hipGetErrorString(e));
+  return SN_OK;
+}
+
+sn_status sn_bptt_backward(const sn_bptt_desc* d, const float* W_cat, const float* x, const float* dcounts,
+                           const void* workspace, float* dW_cat, void* hip_stream) {
+  if (!bptt_desc_ok(d)) return fail(SN_EINVAL, "invalid BPTT descriptor (N must be a positive multiple of 32)");
+  if (!W_cat || !x || !dcounts || !workspace || !dW_cat) return fail(SN_EINVAL, "null pointer");
+  const hipError_t e = bptt_backward(*d, W_cat, x, dcounts, workspace, dW_cat, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(SN_EDEVICE, "BPTT backward: %s", hipGetErrorString(e));
+  return SN_OK;
+}
+
 void sn_batch_destroy(sn_batch* bt) {
   if (!bt) return;
   (void)hipStreamSynchronize(bt->stream);

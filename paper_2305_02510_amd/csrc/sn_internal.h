@@ -161,6 +161,14 @@ struct BatchArgs {
 constexpr int kBatchThreads = 256;
 constexpr int kBatchMaxGroups = 16;  // groups per slice: 4 waves x 4 groups per wave
 
+}  // namespace snmi
+#include "../../include/superneuro_mi.h"
+namespace snmi {
+size_t bptt_workspace_bytes(const sn_bptt_desc& d);
+hipError_t bptt_forward(const sn_bptt_desc& d, const float* W, const float* x, float* counts, void* ws, hipStream_t s);
+hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, const float* dcounts, const void* ws,
+                         float* dW, hipStream_t s);
+
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, bool recs_lds, bool ring_lds);
 size_t lds_limit();

@@ -317,3 +317,37 @@ def by_name(name: str, seed: Optional[int] = None) -> Network:
     }
     fn, default_seed = table[name]
     return fn(default_seed if seed is None else seed)
+
+
+@dataclasses.dataclass
+class BpttProblem:
+    """Recurrent LIF layer training problem: weights, input spikes, target rates."""
+    W_rec: np.ndarray     # float32 [N][N], dyadic
+    W_in: np.ndarray      # float32 [Nin][N], dyadic
+    x: np.ndarray         # uint8 [T][B][Nin]
+    target: np.ndarray    # float32 [N]
+    theta: float = 1.0
+    leak: float = 0.0625
+    reset: float = 0.0
+    slope: float = 10.0
+    checkpoint: int = 50
+
+    @property
+    def shape(self):
+        T, B, Nin = self.x.shape
+        return self.W_rec.shape[0], Nin, B, T
+
+
+def bptt_problem(seed: int = 5, n: int = 2048, n_in: int = 256, trials: int = 128, steps: int = 200,
+                 in_k=(0, 8), drive_p: float = 0.05, checkpoint: int = 50) -> BpttProblem:
+    """Surrogate-gradient training workload: recurrent N = 2048 with the
+    balanced dense weights of the dense-trials net (dyadic, |w| <= 0.25,
+    delay 1), 256 input sources spiking Bernoulli(0.05) into the layer through
+    W_in = k/64 (k uniform in [0, 8]), 128 trials, T = 200, target rates
+    uniform in [0, 0.2], checkpoint every 50 steps; threshold 1, reset 0,
+    leak 2^-4, no refractory period, surrogate slope 10."""
+    W_rec = balanced_dense_weights(n, rng_for(seed, "w"), rng_for(seed, "sel"))
+    W_in = _dyadic_uniform(rng_for(seed, "w", 1), in_k[0], in_k[1], (n_in, n)).astype(np.float32)
+    x = _bernoulli_raster(rng_for(seed, "inp"), (steps, trials, n_in), drive_p)
+    target = rng_for(seed, "target").uniform(0.0, 0.2, size=n).astype(np.float32)
+    return BpttProblem(W_rec, W_in, x, target, checkpoint=checkpoint)

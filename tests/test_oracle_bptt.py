@@ -17,8 +17,9 @@ def test_bptt_pin(oracle, pin):
 
 
 BPTT_MUTANTS = {
-    "surrogate_sign": ("return 0.5 * k / (d * d);", "return -0.5 * k / (d * d);"),
-    "surrogate_unscaled": ("return 0.5 * k / (d * d);", "return 1.0 / (d * d);"),
+    "surrogate_sign": ("return 1.0 / (d * d);", "return -1.0 / (d * d);"),
+    "surrogate_scaled": ("return 1.0 / (d * d);", "return 0.5 * k / (d * d);"),
+    "surrogate_not_squared": ("return 1.0 / (d * d);", "return 1.0 / d;"),
     "no_reset_term": ("gcur[i] = a * sg + gv * ((1.0 - st[i]) + (r - Ut[i]) * sg);",
                       "gcur[i] = a * sg + gv * (1.0 - st[i]);"),
     "leak_always_passes": ("double gv = fabs(Vt[i] - r) > lambda ? gnext[i] : 0.0;", "double gv = gnext[i];"),
@@ -30,7 +31,7 @@ BPTT_MUTANTS = {
                               "for (int32_t j = 0; j < N; ++j) dW_in[(size_t)i * N + j] += 0.5 * gcur[j];"),
     "recurrent_gradient_same_step": ("const double* sp = s + ((size_t)(t - 1) * B + b) * N;\n                for (int32_t i = 0; i < N; ++i) {\n                    if (sp[i] == 0.0) continue;\n                    for (int32_t j = 0; j < N; ++j) dW_rec",
                                      "const double* sp = s + ((size_t)(t) * B + b) * N;\n                for (int32_t i = 0; i < N; ++i) {\n                    if (sp[i] == 0.0) continue;\n                    for (int32_t j = 0; j < N; ++j) dW_rec"),
-    "relaxed_range": ("return 0.5 + 0.5 * k * x / (1.0 + k * fabs(x));", "return 0.5 + k * x / (1.0 + k * fabs(x));"),
+    "relaxed_scale": ("return 0.5 + x / (1.0 + k * fabs(x));", "return 0.5 + 0.5 * k * x / (1.0 + k * fabs(x));"),
     "hard_ge": ("(Ut[j] > theta ? 1.0 : 0.0)", "(Ut[j] >= theta ? 1.0 : 0.0)"),
 }
 
