@@ -96,7 +96,8 @@ def bench_single(args, net, kind):
         w_bytes = 2.0 * net.n * net.n
         out["roofline"] = {
             "bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / BF16_PEAK_TFLOPS, 5), "traffic": None, "kernel": "k_dense_step",
+            "frac": round(achieved / BF16_PEAK_TFLOPS, 5), "traffic": None,
+            "kernel": "k_dense_persist" if path == "dense_persist" else "k_dense_step",
             "flops_per_time_step": flops, "us_per_time_step": round(sec_per_tstep * 1e6, 3),
             "weight_stream_GBps": round(w_bytes / sec_per_tstep / 1e9, 1),
             "weight_stream_frac_of_hbm": round(w_bytes / sec_per_tstep / 1e9 / HBM_PEAK_GBS, 4)}

@@ -70,8 +70,10 @@ enum {
   SN_PATH_SMALL = 1,    /* one workgroup per trial runs all requested steps in one launch */
   SN_PATH_STEP = 2,     /* one launch per step: pull delivery over post-neuron groups */
   SN_PATH_PERSIST = 3,  /* one cooperative launch for all steps, grid barrier per step */
-  SN_PATH_DENSE = 4,    /* dense weights on matrix cores (needs sn_load_dense_weights) */
-  SN_PATH_PUSH = 5      /* event-driven: only synapses of spiking neurons are touched (low firing rates) */
+  SN_PATH_DENSE = 4,    /* dense weights on matrix cores (needs sn_load_dense_weights): one cooperative
+                           launch with the weights resident on chip when they fit, else as SN_PATH_DENSE_STEP */
+  SN_PATH_PUSH = 5,     /* event-driven: only synapses of spiking neurons are touched (low firing rates) */
+  SN_PATH_DENSE_STEP = 6  /* dense weights on matrix cores, one launch per step */
 };
 
 /* Device-memory allocator.  alloc returns device memory of at least `bytes`

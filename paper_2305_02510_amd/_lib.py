@@ -10,8 +10,9 @@ LIB_PATH = os.path.join(HERE, "libsnmi.so")
 SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ESTATE, SN_ERANGE, SN_EINEXACT = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "SN_OK", -1: "SN_EINVAL", -2: "SN_ENOMEM", -3: "SN_EDEVICE", -4: "SN_ESTATE",
                 -5: "SN_ERANGE", -6: "SN_EINEXACT"}
-PATH_AUTO, PATH_SMALL, PATH_STEP, PATH_PERSIST, PATH_DENSE, PATH_PUSH = 0, 1, 2, 3, 4, 5
-PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense", 5: "push", 6: "batch"}
+PATH_AUTO, PATH_SMALL, PATH_STEP, PATH_PERSIST, PATH_DENSE, PATH_PUSH, PATH_DENSE_STEP = 0, 1, 2, 3, 4, 5, 6
+PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense", 5: "push", 6: "dense_step",
+              7: "batch", 8: "dense_persist"}
 
 # Every symbol the header declares.
 EXPORTS = [

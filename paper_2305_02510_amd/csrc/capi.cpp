@@ -156,16 +156,19 @@ sn_status ensure_rows(sn_net* n, int64_t rows) {
 // Chooses where the persistent kernel keeps records and the spike ring;
 // false if the slice plan cannot run at all.
 bool fit_plan(const DevNet& d, SlicePlan& p) {
-  if (p.P < 1 || sim_npt(p.ng_max) > 8) return false;
+  if (p.P < 1 || sim_npt(p.ng_max, p.max_recs) > 8) return false;
   // the spike ring goes to LDS whenever it fits beside the accumulators: a
-  // global ring costs a device-scope load per synapse
-  const bool ring_fits = sim_lds_bytes(d, p.ng_max, 0, false, true) <= 96 * 1024;
-  const bool opts[4][2] = {{true, true}, {true, false}, {false, true}, {false, false}};
+  // global ring costs a device-scope load per synapse; chunk headers go to
+  // LDS whenever they fit (they are 1/32 of the record bytes)
+  const bool ring_fits = sim_lds_bytes(d, p.ng_max, 0, 0, false, true, false) <= 96 * 1024;
+  const bool opts[8][3] = {{true, true, true},   {true, true, false},  {false, true, true},  {false, true, false},
+                           {true, false, true},  {true, false, false}, {false, false, true}, {false, false, false}};
   for (const auto& o : opts) {
     if (ring_fits && !o[1]) continue;
-    if (sim_lds_bytes(d, p.ng_max, p.max_recs, o[0], o[1]) <= lds_limit()) {
+    if (sim_lds_bytes(d, p.ng_max, p.max_recs, p.max_chunks, o[0], o[1], o[2]) <= lds_limit()) {
       p.recs_lds = o[0];
       p.ring_lds = o[1];
+      p.hdr_lds = o[2];
       return true;
     }
   }
@@ -234,6 +237,8 @@ SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
   a.P = dp.host.P;
   a.ng_max = dp.host.ng_max;
   a.max_recs = dp.host.max_recs;
+  a.max_chunks = dp.host.max_chunks;
+  a.hdr_lds = dp.host.hdr_lds ? 1 : 0;
   return a;
 }
 
@@ -334,7 +339,8 @@ sn_status run_push(sn_net* n, int32_t t0, int32_t steps) {
   return SN_OK;
 }
 
-constexpr int32_t kPathBatch = 6;  // sn_get_progress after a batch run
+constexpr int32_t kPathBatch = 7;          // sn_get_progress after a batch run
+constexpr int32_t kPathDensePersist = 8;   // SN_PATH_DENSE ran as one cooperative launch
 
 bool on_device_ok(sn_net* n) {
   int cur = -1;
@@ -395,7 +401,7 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     if (n->poisoned) return fail(SN_ESTATE, "network %d is poisoned", k);
     if (!n->synapses_loaded) return fail(SN_ESTATE, "network %d has no synapses", k);
     if (n->device != v[0]->device) return fail(SN_EINVAL, "networks are on different devices");
-    if (batch_lds_bytes(n->d, 0) > 96 * 1024) return fail(SN_ERANGE, "network %d: spike ring too large for a batch", k);
+    if (batch_lds_bytes(n->d, 0, 0) > 96 * 1024) return fail(SN_ERANGE, "network %d: spike ring too large for a batch", k);
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v[0]->device) != hipSuccess) {
@@ -414,8 +420,12 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
   bt->nets = v;
   bt->stream = v[0]->stream;
   // workgroups resident at once, for the largest LDS any network needs
+  // LDS per workgroup: the largest spike ring + accumulators, plus room for
+  // the chunk headers of a slice (headers that do not fit stay in global memory)
   size_t lds = 0;
-  for (sn_net* n : v) lds = std::max(lds, batch_lds_bytes(n->d, std::min<int32_t>(n->d.G, kBatchMaxGroups)));
+  for (sn_net* n : v) lds = std::max(lds, batch_lds_bytes(n->d, std::min<int32_t>(n->d.G, kBatchMaxGroups), 0));
+  lds = std::min<size_t>(lds + 16 * 1024, 160 * 1024 - 64);
+  const size_t lds_budget = lds;
   const int per_cu = batch_blocks_per_cu(lds);
   if (per_cu < 1) {
     delete bt;
@@ -443,7 +453,6 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
   bt->plans.resize(count);
   bt->plan_off.resize(count);
   std::vector<int32_t> tables;
-  lds = 0;
   for (int32_t k = 0; k < count; ++k) {
     sn_net* n = v[k];
     SlicePlan p = partition_groups(n->layout, n->d.G, P[k], kBatchMaxGroups);
@@ -454,7 +463,7 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     bt->plan_off[k] = tables.size();
     tables.insert(tables.end(), p.wg_group.begin(), p.wg_group.end());
     tables.insert(tables.end(), p.wg_chunk.begin(), p.wg_chunk.end());
-    lds = std::max(lds, batch_lds_bytes(n->d, p.ng_max));
+    p.hdr_lds = batch_lds_bytes(n->d, p.ng_max, p.max_chunks) <= lds_budget;
     bt->plans[k] = std::move(p);
   }
   bt->lds = lds;
@@ -535,6 +544,8 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
     a.P = p.P;
     a.ng_max = p.ng_max;
     a.max_recs = p.max_recs;
+    a.max_chunks = p.max_chunks;
+    a.hdr_lds = p.hdr_lds ? 1 : 0;
     bt->descs[k].team = a;
     bt->descs[k].single = a;
     if (p.P > 1) {
@@ -865,7 +876,7 @@ sn_status sn_set_input_spikes_device(sn_net* n, int32_t t0, int32_t n_steps, con
 sn_status sn_set_path(sn_net* n, int32_t path) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
-  if (path < SN_PATH_AUTO || path > SN_PATH_PUSH) return fail(SN_ERANGE, "unknown path %d", path);
+  if (path < SN_PATH_AUTO || path > SN_PATH_DENSE_STEP) return fail(SN_ERANGE, "unknown path %d", path);
   n->path = path;
   return SN_OK;
 }
@@ -908,6 +919,7 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
       break;
     }
     case SN_PATH_STEP:
+      SN_HIP(n, prepare_step_kernel(n->d));
       st = run_per_step(n, SN_PATH_STEP, n->t, n_steps);
       if (st != SN_OK) return st;
       break;
@@ -916,10 +928,20 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
       if (st != SN_OK) return st;
       break;
     case SN_PATH_DENSE:
+    case SN_PATH_DENSE_STEP: {
       if (!n->dense_loaded) return fail(SN_ESTATE, "the dense path needs sn_load_dense_weights");
+      const int64_t wgs = static_cast<int64_t>(n->d.Npad / 16) * ((n->d.B + 63) / 64);
+      if (path == SN_PATH_DENSE && wgs <= kMaxCoopGroups && dense_persist_lds_bytes(n->kpad) <= lds_limit()) {
+        DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad};
+        SN_HIP(n, launch_dense_persist(a, n->slice_flags, n->status, n->t, n_steps, n->stream));
+        n->t += n_steps;
+        n->last_path = kPathDensePersist;
+        return SN_OK;
+      }
       st = run_per_step(n, SN_PATH_DENSE, n->t, n_steps);
       if (st != SN_OK) return st;
       break;
+    }
     default:
       return fail(SN_ERANGE, "path %d is not available in this build", path);
   }

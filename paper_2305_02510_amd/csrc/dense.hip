@@ -134,6 +134,185 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_step(const DenseArgs a,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent dense kernel: all requested steps in one cooperative launch.
+// Workgroup (c, tb) keeps its 16-column slice of W in LDS for the whole run
+// (kpad x 16 bfloat16: 128 KB at N = 4096), so the weights are read from HBM
+// once per launch instead of once per step; V and the refractory counters of
+// its 64 x 16 neurons stay in registers.  Each step it
+//   1. waits until every workgroup of its trial block has published step t-1
+//      (one flag per workgroup, 256 bytes apart, device-scope loads),
+//   2. loads the spike words of step t-1 it needs straight from the raster
+//      with device-scope loads (no LDS staging),
+//   3. multiplies on the matrix cores as k_dense_step does,
+//   4. updates its neurons and stores its 16 spike bits per trial with
+//      device-scope 16-bit stores, waits for them to complete, and publishes
+//      step t.  Waits are bounded (a timeout sets *status and every wave
+//      exits; the other workgroups then time out the same way).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kDenseSpinLimit = 1u << 22;
+
+__global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs a, uint32_t* flags, uint32_t* status,
+                                                                 int t0, int steps) {
+  const DevNet& n = a.n;
+  const int c = blockIdx.x;
+  const int tb = blockIdx.y;
+  const int ncol = gridDim.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;
+  const int li = lane & 15;
+  const int J = a.kpad / 128;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int abort_flag;
+  uint4* tab = reinterpret_cast<uint4*>(smem);                       // [256]
+  float* part = reinterpret_cast<float*>(tab + 256);                 // [4][64][17]
+  uint4* wl = reinterpret_cast<uint4*>(part + 4 * kDenseTrials * 17);  // [J][4][64] weight fragments
+
+  {
+    const uint32_t x = static_cast<uint32_t>(tid);
+    uint32_t wv[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      wv[h] = (((x >> (2 * h)) & 1u) ? 0x3F80u : 0u) | (((x >> (2 * h + 1)) & 1u) ? 0x3F800000u : 0u);
+    tab[tid] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+  }
+  const uint4* wsrc = reinterpret_cast<const uint4*>(a.wt) + static_cast<size_t>(c) * J * 4 * 64;
+  for (int i = tid; i < J * 4 * 64; i += kDenseThreads) wl[i] = wsrc[i];
+  if (tid == 0) abort_flag = 0;
+
+  // neuron state: lane (q, li) of wave w, pass k -> trial 16w + 4k + q, column li
+  const int col = 16 * c + li;
+  const float th = n.theta[col], lam = n.leak[col], rs = n.reset[col], amp = n.amp[col];
+  const int R = n.refr[col];
+  float V[4];
+  int ref[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = tb * kDenseTrials + 16 * wave + 4 * k + q;
+    V[k] = 0.f;
+    ref[k] = 0;
+    if (b < n.B) {
+      V[k] = n.V[static_cast<size_t>(b) * n.Npad + col];
+      ref[k] = n.ref[static_cast<size_t>(b) * n.Npad + col];
+    }
+  }
+  __syncthreads();
+
+  const uint32_t* r32 = reinterpret_cast<const uint32_t*>(n.raster);
+  const uint16_t* e16 = reinterpret_cast<const uint16_t*>(n.ext);
+  uint16_t* o16 = reinterpret_cast<uint16_t*>(n.raster);
+  uint32_t* myflags = flags + static_cast<size_t>(tb) * ncol * 64;
+  const int g = c >> 2, part16 = c & 3;
+  const int j0 = wave * J / 4, j1 = (wave + 1) * J / 4;
+
+  for (int t = t0; t < t0 + steps; ++t) {
+    if (t > t0) {
+      for (int v = tid; v < ncol; v += kDenseThreads) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&myflags[v * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < static_cast<uint32_t>(t)) {
+          if (++spins > kDenseSpinLimit) {
+            abort_flag = 1;
+            __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      if (abort_flag) return;  // uniform: read after the barrier
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (t >= 1) {
+      for (int j = j0; j < j1; ++j) {
+        uint32_t sw[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int b = tb * kDenseTrials + 16 * m + li;
+          const int wi = 4 * j + q;
+          sw[m] = (b < n.B && wi < 2 * n.G)
+                      ? __hip_atomic_load(&r32[row_word(n, t - 1, b, 0) * 2 + wi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      : 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const bf16x8 bfrag = __builtin_bit_cast(bf16x8, wl[(j * 4 + s) * 64 + lane]);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const bf16x8 afrag = __builtin_bit_cast(bf16x8, tab[(sw[m] >> (8 * s)) & 0xFFu]);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[m], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[(wave * kDenseTrials + 16 * m + 4 * q + r) * 17 + li] = acc[m][r];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int tl = 16 * wave + 4 * k + q;
+      const int b = tb * kDenseTrials + tl;
+      bool s = false;
+      if (b < n.B) {
+        float syn = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) syn += part[(w * kDenseTrials + tl) * 17 + li];
+        const bool ext = (e16[row_word(n, t, b, g) * 4 + part16] >> li) & 1u;
+        s = lif_update(V[k], ref[k], syn, ext, th, lam, rs, amp, R);
+      }
+      const uint64_t bits = __ballot(s);
+      if (li == 0 && b < n.B)
+        __hip_atomic_store(&o16[row_word(n, t, b, g) * 4 + part16], static_cast<uint16_t>(bits >> (16 * q)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // publish step t once this workgroup's spike words are complete
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_store(&myflags[c * 64], static_cast<uint32_t>(t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = tb * kDenseTrials + 16 * wave + 4 * k + q;
+    if (b < n.B) {
+      n.V[static_cast<size_t>(b) * n.Npad + col] = V[k];
+      n.ref[static_cast<size_t>(b) * n.Npad + col] = static_cast<uint8_t>(ref[k]);
+    }
+  }
+}
+
+size_t dense_persist_lds_bytes(int32_t kpad) {
+  return 256 * sizeof(uint4) + 4 * kDenseTrials * 17 * sizeof(float) + static_cast<size_t>(kpad) * 16 * sizeof(uint16_t);
+}
+
+__global__ void k_dense_clear_flags(uint32_t* flags, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) flags[i] = 0u;
+}
+
+// Cooperative launch when every workgroup fits on the device at once;
+// returns hipErrorCooperativeLaunchTooLarge otherwise (the caller falls back
+// to per-step launches).
+hipError_t launch_dense_persist(const DenseArgs& a, uint32_t* flags, uint32_t* status, int32_t t0, int32_t steps,
+                                hipStream_t s) {
+  const size_t lds = dense_persist_lds_bytes(a.kpad);
+  const void* fn = reinterpret_cast<const void*>(&k_dense_persist);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  const dim3 grid(a.n.Npad / 16, (a.n.B + kDenseTrials - 1) / kDenseTrials);
+  const int nflags = static_cast<int>(grid.x * grid.y * 64);
+  hipLaunchKernelGGL(k_dense_clear_flags, dim3((nflags + 255) / 256), dim3(256), 0, s, flags, nflags);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[] = {const_cast<DenseArgs*>(&a), &flags, &status, &t0, &steps};
+  return hipLaunchCooperativeKernel(fn, grid, dim3(kDenseThreads), args, static_cast<unsigned>(lds), s);
+}
+
 size_t dense_lds_bytes(int32_t kpad) {
   return 256 * sizeof(uint4) + 4 * kDenseTrials * 17 * sizeof(float) +
          static_cast<size_t>(kDenseTrials) * (kpad / 32 + 1) * sizeof(uint32_t);

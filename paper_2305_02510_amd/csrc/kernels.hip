@@ -48,10 +48,17 @@ __device__ __forceinline__ void store_dev(uint64_t* p, uint64_t v) {
 // chunk): four independent record / bit / accumulate chains per lane.  When
 // records stream from global memory, the next chunk's records are loaded
 // while the current one is processed.
+// Header of chunk c: from LDS (lhdr[c - hoff]) when staged there, else global.
+struct Hdr {
+  const uint2* lhdr;
+  int hoff;
+  bool in_lds;
+};
+
 template <bool RECS_LDS>
-__device__ __forceinline__ void load_chunk(const DevNet& n, const Rec* lrec, int c, int lane, int r0, Rec (&rc)[4],
-                                           int& lg_g, int& cnt) {
-  const uint2 ch = n.chunks[c];
+__device__ __forceinline__ void load_chunk(const DevNet& n, const Rec* lrec, const Hdr& hdr, int c, int lane, int r0,
+                                           Rec (&rc)[4], int& lg_g, int& cnt) {
+  const uint2 ch = hdr.in_lds ? hdr.lhdr[c - hdr.hoff] : n.chunks[c];
   const int start = static_cast<int>(ch.x);
   lg_g = static_cast<int>(ch.y & 0xFFFFFu);
   cnt = static_cast<int>(ch.y >> 20);
@@ -63,18 +70,20 @@ __device__ __forceinline__ void load_chunk(const DevNet& n, const Rec* lrec, int
   }
 }
 
+// Chunk headers come from LDS when the slice's headers were staged there, so
+// a record load never waits on a dependent global load.
 template <bool RECS_LDS, bool RING_LDS>
-__device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const uint32_t* ring,
+__device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const Hdr& hdr, const uint32_t* ring,
                                         const uint64_t* mring, float* acc, int c, int c_end, int nwave,
                                         int lane, int g0, int r0, int t, int cur, int Dr, int W32) {
   if (c >= c_end) return;
   Rec rc[4];
   int g = 0, cnt = 0;
-  load_chunk<RECS_LDS>(n, lrec, c, lane, r0, rc, g, cnt);
+  load_chunk<RECS_LDS>(n, lrec, hdr, c, lane, r0, rc, g, cnt);
   for (; c < c_end; c += nwave) {
     Rec nx[4];
     int ng = 0, ncnt = 0;
-    if (!RECS_LDS && c + nwave < c_end) load_chunk<RECS_LDS>(n, lrec, c + nwave, lane, r0, nx, ng, ncnt);
+    if (!RECS_LDS && c + nwave < c_end) load_chunk<RECS_LDS>(n, lrec, hdr, c + nwave, lane, r0, nx, ng, ncnt);
     uint32_t bit[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -97,7 +106,7 @@ __device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const 
     }
     if (c + nwave < c_end) {
       if (RECS_LDS) {
-        load_chunk<RECS_LDS>(n, lrec, c + nwave, lane, r0, rc, g, cnt);
+        load_chunk<RECS_LDS>(n, lrec, hdr, c + nwave, lane, r0, rc, g, cnt);
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u) rc[u] = nx[u];
@@ -131,7 +140,12 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
 
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);
   float* acc = reinterpret_cast<float*>(ring + (RING_LDS ? Dr * W32 : 0));
-  Rec* lrec = reinterpret_cast<Rec*>(acc + a.ng_max * kGroup);  // offsets are multiples of 8 bytes
+  uint2* lhdr = reinterpret_cast<uint2*>(acc + a.ng_max * kGroup);  // offsets are multiples of 8 bytes
+  Rec* lrec = reinterpret_cast<Rec*>(lhdr + (a.hdr_lds ? a.max_chunks : 0));
+  // chunk headers of both parts: part A at lhdr[0 .. nA), part B after it
+  const int nA = cA1 - cA0;
+  const Hdr hA{lhdr, cA0, a.hdr_lds != 0};
+  const Hdr hB{lhdr + nA, cB0, a.hdr_lds != 0};
 
   if (tid == 0) abort_flag = 0;
   __syncthreads();
@@ -141,6 +155,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
   for (int i = tid; i < ng * kGroup; i += nthr) acc[i] = 0.f;
   if (RECS_LDS) {
     for (int i = tid; i < nrec; i += nthr) lrec[i] = n.recs[r0 + i];
+  }
+  if (a.hdr_lds) {
+    for (int i = tid; i < nA; i += nthr) lhdr[i] = n.chunks[cA0 + i];
+    for (int i = tid; i < cB1 - cB0; i += nthr) lhdr[nA + i] = n.chunks[cB0 + i];
   }
   __syncthreads();
   if (RING_LDS) {  // history of the steps before t0 (rows < 0 stay zero)
@@ -188,7 +206,7 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     }
     const int cur = t % Dr;
     // delay >= 2: every needed row is already held
-    deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, acc, cA0 + wave, cA1, nwave, lane, g0, r0, t, cur, Dr, W32);
+    deliver<RECS_LDS, RING_LDS>(n, lrec, hA, ring, mring, acc, cA0 + wave, cA1, nwave, lane, g0, r0, t, cur, Dr, W32);
     if (MULTI && t > t0) {
       // receive row t - 1: wait until every slice has published step t - 1
       // (one padded flag per slice), then read the row's tagged words; a tag
@@ -226,7 +244,7 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     __syncthreads();
     if (MULTI && abort_flag) return false;  // uniform: read after the barrier
     // delay 1
-    deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, acc, cB0 + wave, cB1, nwave, lane, g0, r0, t, cur, Dr, W32);
+    deliver<RECS_LDS, RING_LDS>(n, lrec, hB, ring, mring, acc, cB0 + wave, cB1, nwave, lane, g0, r0, t, cur, Dr, W32);
     __syncthreads();
     // fused neuron update; the ballot of a wave is the spike word of its group
 #pragma unroll
@@ -319,7 +337,7 @@ hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
 // queue is empty.  Team slices wait only on slices of the same network, all
 // of which are resident (cooperative launch) and start with their team task.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs ba, int steps) {
+__global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, int steps) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int abort_flag;
   __shared__ int next;
@@ -342,8 +360,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchArgs ba, int
   }
 }
 
-size_t batch_lds_bytes(const DevNet& n, int ng_max) {
-  return static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(ng_max) * kGroup * sizeof(float);
+size_t batch_lds_bytes(const DevNet& n, int ng_max, int max_chunks) {
+  return static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(ng_max) * kGroup * sizeof(float) +
+         static_cast<size_t>(max_chunks) * sizeof(uint2);
 }
 
 int batch_blocks_per_cu(size_t lds) {
@@ -374,8 +393,10 @@ hipError_t launch_zero_i32(int32_t* p, hipStream_t s) {
 constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kMaxNpt = 8;
 
-size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, bool recs_lds, bool ring_lds) {
+size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int max_chunks, bool recs_lds, bool ring_lds,
+                     bool hdr_lds) {
   size_t bytes = static_cast<size_t>(ng_max) * kGroup * sizeof(float);
+  if (hdr_lds) bytes += static_cast<size_t>(max_chunks) * sizeof(uint2);
   if (ring_lds) bytes += static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t);
   if (recs_lds) bytes += static_cast<size_t>(max_recs) * sizeof(Rec);
   return bytes + 64;  // static LDS of the kernel
@@ -383,10 +404,15 @@ size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, bool recs_ld
 
 size_t lds_limit() { return kLdsLimit; }
 
-int sim_threads(int ng_max) { return ng_max * kGroup < 1024 ? ng_max * kGroup : 1024; }
+// Threads of a slice's workgroup: at least one wave per group (the update),
+// and enough waves that delivery has ~8 records per lane, up to 1024.
+int sim_threads(int ng_max, int64_t max_recs) {
+  int64_t thr = std::max<int64_t>(static_cast<int64_t>(ng_max) * kGroup, (max_recs / 8 + 63) / 64 * 64);
+  return static_cast<int>(std::min<int64_t>(thr, 1024));
+}
 
-int sim_npt(int ng_max) {
-  const int nw = sim_threads(ng_max) / kGroup;
+int sim_npt(int ng_max, int64_t max_recs) {
+  const int nw = sim_threads(ng_max, max_recs) / kGroup;
   return (ng_max + nw - 1) / nw;
 }
 
@@ -396,7 +422,7 @@ static hipError_t launch_sim_t(const SimArgs& a, int32_t t0, int32_t steps, hipS
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      static_cast<int>(kLdsLimit - 64));
   if (e != hipSuccess) return e;
-  const dim3 block(sim_threads(a.ng_max));
+  const dim3 block(sim_threads(a.ng_max, a.max_recs));
   if (MULTI) {
     const dim3 grid(a.P, a.n.B);
     void* args[] = {const_cast<SimArgs*>(&a), &t0, &steps};
@@ -409,7 +435,7 @@ static hipError_t launch_sim_t(const SimArgs& a, int32_t t0, int32_t steps, hipS
 template <bool MULTI>
 static hipError_t launch_sim_m(const SimArgs& a, bool rl, bool gl, int32_t t0, int32_t steps, hipStream_t s,
                                size_t lds) {
-  const int npt = sim_npt(a.ng_max);
+  const int npt = sim_npt(a.ng_max, a.max_recs);
   const int np2 = npt <= 1 ? 1 : npt <= 2 ? 2 : npt <= 4 ? 4 : 8;
   const int key = np2 * 4 + (rl ? 2 : 0) + (gl ? 1 : 0);
   switch (key) {
@@ -428,8 +454,8 @@ static hipError_t launch_sim_m(const SimArgs& a, bool rl, bool gl, int32_t t0, i
 }
 
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s) {
-  if (sim_npt(a.ng_max) > kMaxNpt) return hipErrorInvalidValue;
-  const size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, recs_lds, ring_lds) - 64;
+  if (sim_npt(a.ng_max, a.max_recs) > kMaxNpt) return hipErrorInvalidValue;
+  const size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, a.max_chunks, recs_lds, ring_lds, a.hdr_lds != 0) - 64;
   if (lds + 64 > kLdsLimit) return hipErrorInvalidValue;
   if (a.P > 1 || !ring_lds) {
     const hipError_t e = launch_prefill_mailbox(a, t0, s);
@@ -442,19 +468,26 @@ hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0
 
 // ---------------------------------------------------------------------------
 // Per-step pull kernel: workgroup (g, b) accumulates, for trial b, the
-// delayed input of the 64 posts of group g by streaming the group's records
-// (coalesced 8-byte loads, U records per lane in flight), testing the
-// pre-neuron's bit in raster row t - d, and adding w into an LDS accumulator.
-// Wave 0 then applies the neuron update and writes the group's spike word.
+// delayed input of the 64 posts of group g.  It loads the group's records
+// (coalesced 8-byte loads, U per lane in flight) and, at the same time, the D
+// previous raster rows into LDS when they fit (RING), so each record costs
+// one global round trip; the source bit of row t - d is then an LDS read and
+// w is added into an LDS accumulator.  Wave 0 applies the neuron update and
+// writes the group's spike word.
 // ---------------------------------------------------------------------------
-template <int WAVES, int U>
+template <int WAVES, int U, bool RING>
 __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
   __shared__ float acc[kGroup];
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* ring = reinterpret_cast<uint32_t*>(smem);  // [D][2G]: row t - d at (d - 1)
   const int g = blockIdx.x;
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int j = g * kGroup + lane;
+  const int W32 = 2 * n.G;
+  const size_t rstride = static_cast<size_t>(n.B) * n.G;
+  const uint64_t* hist = n.raster + static_cast<size_t>(b) * n.G;
 
   float V = 0.f, th = 0.f, lam = 0.f, rs = 0.f, amp = 0.f;
   int ref = 0, R = 0;
@@ -471,33 +504,55 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
     R = n.refr[j];
     ew = n.ext[row_word(n, t, b, g)];
   }
-  __syncthreads();
-
   const int beg = n.gptr[g];
   const int end = n.gptr[g + 1];
-  const size_t rstride = static_cast<size_t>(n.B) * n.G;
-  const uint64_t* hist = n.raster + static_cast<size_t>(b) * n.G;
-  for (int base = beg + wave * 64 * U; base < end; base += WAVES * 64 * U) {
-    Rec rr[U];
-    bool ok[U];
+  // first batch of records, issued before the history rows
+  Rec rr[U];
+  bool ok[U];
+  int base = beg + wave * 64 * U;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = base + u * 64 + lane;
+    ok[u] = k < end;
+    rr[u] = ok[u] ? n.recs[k] : Rec{0.f, 0u};
+  }
+  if (RING) {
+    for (int i = threadIdx.x; i < n.D * n.G; i += WAVES * 64) {
+      const int d = i / n.G + 1, w = i - (d - 1) * n.G;
+      const int ts = t - d;
+      const uint64_t v = ts >= 0 ? hist[static_cast<size_t>(ts) * rstride + w] : 0ull;
+      ring[(d - 1) * W32 + 2 * w] = static_cast<uint32_t>(v);
+      ring[(d - 1) * W32 + 2 * w + 1] = static_cast<uint32_t>(v >> 32);
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    uint32_t bit[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t m = rr[u].meta;
+      const int d = static_cast<int>((m >> 20) & 63u) + 1;
+      const uint32_t pre = m & 0xFFFFFu;
+      bit[u] = 0u;
+      if (ok[u] && t - d >= 0) {
+        if (RING) {
+          bit[u] = (ring[(d - 1) * W32 + (pre >> 5)] >> (pre & 31u)) & 1u;
+        } else {
+          bit[u] = static_cast<uint32_t>(hist[static_cast<size_t>(t - d) * rstride + (pre >> 6)] >> (pre & 63u)) & 1u;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (bit[u]) atomicAdd(&acc[rr[u].meta >> 26], rr[u].w);
+    }
+    base += WAVES * 64 * U;
+    if (base >= end) break;  // uniform per wave
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = base + u * 64 + lane;
       ok[u] = k < end;
       rr[u] = ok[u] ? n.recs[k] : Rec{0.f, 0u};
-    }
-    uint64_t word[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t m = rr[u].meta;
-      const int ts = t - static_cast<int>((m >> 20) & 63u) - 1;
-      ok[u] = ok[u] && ts >= 0;
-      word[u] = ok[u] ? hist[static_cast<size_t>(ts) * rstride + ((m & 0xFFFFFu) >> 6)] : 0ull;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t m = rr[u].meta;
-      if ((word[u] >> (m & 63u)) & 1ull) atomicAdd(&acc[m >> 26], rr[u].w);
     }
   }
   __syncthreads();
@@ -511,17 +566,40 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
   }
 }
 
-hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s) {
-  // enough waves per group to keep every lane busy with U = 4 records
-  const int per_group = n.G > 0 ? (static_cast<int>(n.nnz / n.G) + 1) : 1;
-  if (per_group > 8 * 64 * 4) {
-    hipLaunchKernelGGL((k_step<16, 4>), dim3(n.G, n.B), dim3(1024), 0, s, n, t);
-  } else if (per_group > 2 * 64 * 4) {
-    hipLaunchKernelGGL((k_step<4, 4>), dim3(n.G, n.B), dim3(256), 0, s, n, t);
+constexpr size_t kStepRingLimit = 64 * 1024;
+
+static size_t step_ring_bytes(const DevNet& n) { return static_cast<size_t>(n.D) * 2 * n.G * sizeof(uint32_t); }
+
+template <int WAVES, int U>
+static hipError_t launch_step_t(const DevNet& n, int32_t t, hipStream_t s) {
+  const size_t ring = step_ring_bytes(n);
+  if (ring <= kStepRingLimit) {
+    hipLaunchKernelGGL((k_step<WAVES, U, true>), dim3(n.G, n.B), dim3(WAVES * 64), ring, s, n, t);
   } else {
-    hipLaunchKernelGGL((k_step<1, 4>), dim3(n.G, n.B), dim3(64), 0, s, n, t);
+    hipLaunchKernelGGL((k_step<WAVES, U, false>), dim3(n.G, n.B), dim3(WAVES * 64), 0, s, n, t);
   }
   return hipGetLastError();
+}
+
+hipError_t prepare_step_kernel(const DevNet& n) {
+  const size_t ring = step_ring_bytes(n);
+  if (ring > kStepRingLimit) return hipSuccess;
+  const void* fns[] = {reinterpret_cast<const void*>(&k_step<16, 8, true>),
+                       reinterpret_cast<const void*>(&k_step<4, 8, true>),
+                       reinterpret_cast<const void*>(&k_step<1, 4, true>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(ring));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s) {
+  // enough waves per group that every lane has its U records in one pass
+  const int per_group = n.G > 0 ? (static_cast<int>(n.nnz / n.G) + 1) : 1;
+  if (per_group > 4 * 64 * 8) return launch_step_t<16, 8>(n, t, s);
+  if (per_group > 64 * 4) return launch_step_t<4, 8>(n, t, s);
+  return launch_step_t<1, 4>(n, t, s);
 }
 
 // ---------------------------------------------------------------------------

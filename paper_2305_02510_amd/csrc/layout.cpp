@@ -121,7 +121,9 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
     p.wg_chunk[i] = L.gchunk[p.wg_group[i]];
     p.wg_chunk[p.wg_group.size() + i] = L.gchunk[G + 1 + p.wg_group[i]];
   }
+  const size_t P1 = p.wg_group.size();
   for (int32_t w = 0; w < p.P; ++w) {
+    p.max_chunks = std::max(p.max_chunks, (p.wg_chunk[w + 1] - p.wg_chunk[w]) + (p.wg_chunk[P1 + w + 1] - p.wg_chunk[P1 + w]));
     p.ng_max = std::max(p.ng_max, p.wg_group[w + 1] - p.wg_group[w]);
     p.max_recs = std::max<int64_t>(p.max_recs, L.gptr[p.wg_group[w + 1]] - L.gptr[p.wg_group[w]]);
   }

@@ -183,9 +183,16 @@ __global__ void k_push_pending(const PushArgs a, int t0) {
   }
 }
 
+// Threads of a slice: one wave per group for the update, at least 4 waves
+// for the delivery of spiking neurons' out-going synapses.
+static int push_threads(int ng_max) {
+  const int thr = ng_max * kGroup < 256 ? 256 : ng_max * kGroup;
+  return thr < 1024 ? thr : 1024;
+}
+
 template <int NPT, bool MULTI>
 static hipError_t launch_push_t(const PushArgs& a, int32_t t0, int32_t steps, hipStream_t s) {
-  const int nthr = a.ng_max * kGroup < 1024 ? a.ng_max * kGroup : 1024;
+  const int nthr = push_threads(a.ng_max);
   const size_t lds = static_cast<size_t>(a.ng_max) * kGroup * sizeof(int);
   const void* fn = reinterpret_cast<const void*>(&k_push<NPT, MULTI>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -199,7 +206,7 @@ static hipError_t launch_push_t(const PushArgs& a, int32_t t0, int32_t steps, hi
 }
 
 hipError_t launch_push(const PushArgs& a, int32_t t0, int32_t steps, hipStream_t s) {
-  const int nthr = a.ng_max * kGroup < 1024 ? a.ng_max * kGroup : 1024;
+  const int nthr = push_threads(a.ng_max);
   const int npt = (a.ng_max + nthr / kGroup - 1) / (nthr / kGroup);
   if (npt > 8 || a.P < 1) return hipErrorInvalidValue;
   const size_t count = static_cast<size_t>(a.n.D + 1) * a.n.B * a.n.Npad;

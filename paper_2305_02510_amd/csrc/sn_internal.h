@@ -48,8 +48,10 @@ struct SlicePlan {
   int32_t P = 0;
   int32_t ng_max = 0;
   int64_t max_recs = 0;
+  int32_t max_chunks = 0;  // most chunk headers of one slice (both parts)
   bool recs_lds = false;
   bool ring_lds = false;
+  bool hdr_lds = false;    // chunk headers copied to LDS at the start of a launch
 };
 
 // Splits groups into `slices` contiguous slices balancing record counts, no
@@ -98,6 +100,8 @@ struct SimArgs {
   int32_t P;
   int32_t ng_max;           // most groups in one slice
   int64_t max_recs;         // most records in one slice
+  int32_t max_chunks;       // most chunk headers in one slice
+  int32_t hdr_lds;          // nonzero: chunk headers are staged in LDS
 };
 
 // Dense delay-1 weights for the matrix-core path, bfloat16, tiled for
@@ -158,8 +162,8 @@ struct BatchArgs {
   int32_t* queue_head; // next queue entry to take (zero before the launch)
 };
 
-constexpr int kBatchThreads = 256;
-constexpr int kBatchMaxGroups = 16;  // groups per slice: 4 waves x 4 groups per wave
+constexpr int kBatchThreads = 512;
+constexpr int kBatchMaxGroups = 32;  // groups per slice: 8 waves x 4 groups per wave
 
 }  // namespace snmi
 #include "../../include/superneuro_mi.h"
@@ -170,20 +174,25 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
                          float* dW, hipStream_t s);
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
-size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, bool recs_lds, bool ring_lds);
+size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int max_chunks, bool recs_lds, bool ring_lds,
+                     bool hdr_lds);
 size_t lds_limit();
-int sim_threads(int ng_max);
-int sim_npt(int ng_max);
+int sim_threads(int ng_max, int64_t max_recs);
+int sim_npt(int ng_max, int64_t max_recs);
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s);
 hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s);
-size_t batch_lds_bytes(const DevNet& n, int ng_max);
+size_t batch_lds_bytes(const DevNet& n, int ng_max, int max_chunks);
 int batch_blocks_per_cu(size_t lds);
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
+hipError_t prepare_step_kernel(const DevNet& n);
 hipError_t launch_dense_step(const DenseArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_push(const PushArgs& a, int32_t t0, int32_t steps, hipStream_t s);
 hipError_t prepare_dense_kernel(int32_t kpad);
+size_t dense_persist_lds_bytes(int32_t kpad);
+hipError_t launch_dense_persist(const DenseArgs& a, uint32_t* flags, uint32_t* status, int32_t t0, int32_t steps,
+                                hipStream_t s);
 size_t dense_lds_bytes(int32_t kpad);
 hipError_t launch_reset_state(const DevNet& n, hipStream_t s);
 hipError_t launch_repack_input(const DevNet& n, int32_t t0, int32_t steps, const uint32_t* bits,

@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import check
 
 PATHS = {"auto": _lib.PATH_AUTO, "small": _lib.PATH_SMALL, "step": _lib.PATH_STEP,
-         "persist": _lib.PATH_PERSIST, "dense": _lib.PATH_DENSE, "push": _lib.PATH_PUSH}
+         "persist": _lib.PATH_PERSIST, "dense": _lib.PATH_DENSE, "push": _lib.PATH_PUSH,
+         "dense_step": _lib.PATH_DENSE_STEP}
 
 
 class TorchAllocator:

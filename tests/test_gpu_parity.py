@@ -223,9 +223,9 @@ def test_dense_trials_small(gpu, oracle):
     for (n, trials, seed) in [(100, 3, 31), (256, 17, 32), (130, 64, 33), (64, 70, 34)]:
         net = wl.dense_trials(seed, n=n, trials=trials, steps=60, drive_p=0.05)
         res = oracle.run_dense(net)
-        for path in ("dense", "step", "persist", "push"):
-            s, V, r, used = simulate(gpu, net, path)
-            assert used == path
+        for path in ("dense", "dense_step", "step", "persist", "push"):
+            s, V, r, used = simulate(gpu, net, path, chunks=[25, 35])
+            assert used == {"dense": "dense_persist"}.get(path, path) or (path == "dense" and used == "dense")
             assert_parity(net, res, s, V, r, f"{path} n={n} trials={trials}")
 
 
@@ -235,7 +235,7 @@ def test_dense_trials_full_sampled(gpu, oracle):
     net = wl.dense_trials(3)
     g = gpu.from_workload(net)
     g.run(net.steps)
-    assert g.progress[1] == "dense"
+    assert g.progress[1] == "dense_persist"
     spikes = g.read_raster(0, net.steps)
     V, ref = g.read_state()
     g.close()
