@@ -69,6 +69,21 @@ def cpu_threads_used():
     return 1
 
 
+def measured_traffic(summary: str, source: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary under
+    profiles/, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    vals = dict(l.split(None, 1) for l in open(path) if l.strip() and not l.startswith("#"))
+    cur = hashlib.sha256(open(os.path.join(ROOT, "paper_2305_02510_amd", "csrc", source), "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256", "").strip() != cur:
+        return None
+    return {"bytes_per_launch": int(float(vals["traffic_bytes_per_launch"])),
+            "time_steps_per_launch": int(vals["time_steps_per_launch"]), "source": f"profiles/{summary}"}
+
+
 def bench_single(args, net, kind):
     """One net (possibly many trials): reset + run(T) per benchmark step."""
     from paper_2305_02510_amd import Network
@@ -106,10 +121,17 @@ def bench_single(args, net, kind):
         achieved = bytes_step / sec_per_tstep / 1e9
         kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)", "step": "k_step",
                   "push": "k_push"}.get(path, path)
+        traffic = None
+        if path == "persist" and net.name.startswith("large_sparse_n10000"):
+            traffic = measured_traffic("large_sparse_k_sim_persist_hbm_traffic.txt", "kernels.hip")
         out["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": kernel,
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": traffic["bytes_per_launch"] if traffic else None, "kernel": kernel,
             "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3)}
+        if traffic:
+            out["roofline"]["traffic_note"] = (f"HBM bytes per launch of {traffic['time_steps_per_launch']} time steps "
+                                               f"(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; {traffic['source']})")
     if not args.no_cpu_baseline:
         import oracle
         orc = oracle.default()
@@ -210,7 +232,19 @@ def main():
     ap.add_argument("--path", default="auto")
     ap.add_argument("--cpu-trials", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of 256 MiB (read 256 MiB, write 256 MiB) and exit; "
+                         "profiled with the same counters it scales FETCH_SIZE / WRITE_SIZE to bytes")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; how the simulation would shard "
                                    "across GPUs is described in DESIGN.md but not built"}))

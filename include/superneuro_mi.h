@@ -177,9 +177,9 @@ sn_status sn_reset_state(sn_net* net);
 /* Selects the execution strategy (SN_PATH_*); checked at the next sn_run. */
 sn_status sn_set_path(sn_net* net, int32_t path);
 
-/* Number of slices (workgroups per trial) of SN_PATH_PERSIST: 0 picks the
- * fewest slices whose synapse records fit in on-chip memory (or one per
- * compute unit when they cannot); 1..256 requests a count, raised to the
+/* Number of slices (workgroups per trial) of SN_PATH_PERSIST: 0 picks one
+ * slice per 64-neuron group, up to one per compute unit; 1..256 requests a
+ * count, raised to the
  * minimum a slice can hold (128 groups of 64 neurons per slice) and lowered
  * to the number of groups.  A tuning knob: results do not change.
  * Errors: SN_ERANGE. */

@@ -177,36 +177,15 @@ bool fit_plan(const DevNet& d, SlicePlan& p) {
 
 constexpr int32_t kMaxCoopGroups = 256;  // one workgroup per CU of an MI355X
 
-// Slice plan for the multi-workgroup persistent kernel: the fewest slices
-// whose records fit in LDS (fewest barrier participants), else one slice per
-// CU streaming records from global memory.
+// Slice plan for the multi-workgroup persistent kernel: as many slices as
+// groups, up to one per compute unit (a slice's delivery time grows with its
+// records while the spike exchange costs about the same for any count).
 SlicePlan plan_persist(const DevNet& d, const HostLayout& L, int32_t slices_req) {
   const int32_t pmax = std::max(1, kMaxCoopGroups / d.B);
   const int32_t top = std::min(d.G, pmax);
-  if (slices_req > 0) {
-    // a slice holds at most 128 groups (8 per wave of a 1024-thread workgroup)
-    const int32_t lo_req = std::max(slices_req, (d.G + 127) / 128);
-    SlicePlan p = partition_groups(L, d.G, std::min(lo_req, top), 128);
-    if (!fit_plan(d, p)) p.P = 0;
-    return p;
-  }
-  int32_t lo = 1, hi = top;
-  auto resident = [&](int32_t P, SlicePlan* out) {
-    SlicePlan p = partition_groups(L, d.G, P, 128);
-    const bool ok = fit_plan(d, p) && p.recs_lds;
-    if (out) *out = p;
-    return ok;
-  };
-  if (resident(hi, nullptr)) {
-    while (lo < hi) {
-      const int32_t mid = lo + (hi - lo) / 2;
-      if (resident(mid, nullptr)) hi = mid; else lo = mid + 1;
-    }
-    SlicePlan p;
-    resident(lo, &p);
-    return p;
-  }
-  SlicePlan p = partition_groups(L, d.G, top, 128);
+  // a slice holds at most 128 groups (8 per wave of a 1024-thread workgroup)
+  const int32_t want = slices_req > 0 ? std::max(slices_req, (d.G + 127) / 128) : top;
+  SlicePlan p = partition_groups(L, d.G, std::min(want, top), 128);
   if (!fit_plan(d, p)) p.P = 0;
   return p;
 }
@@ -232,7 +211,6 @@ SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
   a.wg_group = static_cast<const int32_t*>(dp.wg);
   a.wg_chunk = static_cast<const int32_t*>(dp.wg) + dp.host.P + 1;
   a.mailbox = n->mailbox;
-  a.flags = n->slice_flags;
   a.status = n->status;
   a.P = dp.host.P;
   a.ng_max = dp.host.ng_max;
@@ -539,7 +517,6 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
     a.wg_group = tables + bt->plan_off[k];
     a.wg_chunk = tables + bt->plan_off[k] + p.P + 1;
     a.mailbox = n->mailbox;
-    a.flags = n->slice_flags;
     a.status = n->status;
     a.P = p.P;
     a.ng_max = p.ng_max;
@@ -904,7 +881,10 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
     // one workgroup when its records and spike ring fit in LDS, otherwise one
     // launch per step
     if (n->dense_loaded) path = SN_PATH_DENSE;
-    else path = (n->small.ok && n->small.host.recs_lds && n->small.host.ring_lds) ? SN_PATH_SMALL : SN_PATH_STEP;
+    else if (n->small.ok && n->small.host.recs_lds && n->small.host.ring_lds) path = SN_PATH_SMALL;
+    else if (n->persist.ok && n->persist.host.P > 1 && n->persist.host.recs_lds && n->persist.host.ring_lds)
+      path = SN_PATH_PERSIST;
+    else path = SN_PATH_STEP;
   }
   switch (path) {
     case SN_PATH_SMALL:

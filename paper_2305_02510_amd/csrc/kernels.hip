@@ -24,8 +24,8 @@ namespace snmi {
 // Because tag and data share one atomic location, a reader that sees tag
 // t + 1 sees that step's bits; no cache writeback or invalidate is needed.
 // A workgroup first delivers its delay >= 2 synapses (history it already
-// holds), then waits for the tags of row t - 1 from every slice, then delivers
-// its delay-1 synapses.  A slice runs at most one step ahead of the slowest,
+// holds), then reads row t - 1, waiting on any word whose tag is not yet
+// t, then delivers its delay-1 synapses.  A slice runs at most one step ahead of the slowest,
 // so a slot is never rewritten before every reader is done with it.  Without
 // an LDS ring the bits are read from the mailbox ring itself.  Every wait is
 // bounded: after kSpinLimit polls the workgroup records a timeout in *status
@@ -205,30 +205,20 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
       ew_next[k] = (lg < ng && t + 1 < t0 + steps) ? n.ext[row_word(n, t + 1, b, g0 + lg)] : 0ull;
     }
     const int cur = t % Dr;
+    // receive row t - 1: every word carries its step tag.  The first read of
+    // this thread's word is issued before the delay >= 2 delivery, which
+    // hides its latency; a word whose tag is not yet t is read again.
+    const int prev = (t > 0 ? t - 1 : 0) % Dr;
+    const bool receive = MULTI && t > t0;
+    uint64_t early = 0;
+    if (receive && tid < W32) early = load_dev(mring + static_cast<size_t>(prev) * n.B * W32 + tid);
     // delay >= 2: every needed row is already held
     deliver<RECS_LDS, RING_LDS>(n, lrec, hA, ring, mring, acc, cA0 + wave, cA1, nwave, lane, g0, r0, t, cur, Dr, W32);
-    if (MULTI && t > t0) {
-      // receive row t - 1: wait until every slice has published step t - 1
-      // (one padded flag per slice), then read the row's tagged words; a tag
-      // is checked on every word and a word not yet visible is waited for
-      const uint32_t* flags = a.flags + static_cast<size_t>(b) * a.P * 64;
-      for (int v = tid; v < a.P; v += nthr) {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&flags[v * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < static_cast<uint32_t>(t)) {
-          if (++spins > kSpinLimit) {
-            abort_flag = 1;
-            __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-        }
-      }
-      __syncthreads();
-      if (abort_flag) return false;  // uniform: read after the barrier
-      const int prev = (t - 1) % Dr;
+    if (receive) {
       const uint64_t tag = static_cast<uint64_t>(t);
       for (int i = tid; i < W32; i += nthr) {
         const uint64_t* p = mring + static_cast<size_t>(prev) * n.B * W32 + i;
-        uint64_t v = load_dev(p);
+        uint64_t v = i == tid ? early : load_dev(p);
         uint32_t spins = 0;
         while ((v >> 32) != tag) {
           if (++spins > kSpinLimit) {
@@ -265,14 +255,6 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
       }
       ew[k] = ew_next[k];
     }
-    if (MULTI) {
-      // publish step t once every mailbox word of this slice is written
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (tid == 0)
-        __hip_atomic_store(&a.flags[(static_cast<size_t>(b) * a.P + w) * 64], static_cast<uint32_t>(t + 1),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     __syncthreads();
   }
 #pragma unroll
@@ -307,10 +289,7 @@ __global__ void k_prefill_mailbox(const SimArgs a, int t0) {
   const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int Dr = n.D + 1;
   const size_t total = static_cast<size_t>(Dr) * n.B * W32;
-  if (i >= total) {
-    if (a.P > 1 && i < static_cast<size_t>(n.B) * a.P * 64) a.flags[i] = 0u;
-    return;
-  }
+  if (i >= total) return;
   const int word = static_cast<int>(i % W32);
   const int b = static_cast<int>((i / W32) % n.B);
   const int slot = static_cast<int>(i / (static_cast<size_t>(W32) * n.B));
@@ -322,11 +301,10 @@ __global__ void k_prefill_mailbox(const SimArgs a, int t0) {
     v = (static_cast<uint64_t>(r + 1) << 32) | ((wv >> (32 * (word & 1))) & 0xFFFFFFFFull);
   }
   a.mailbox[i] = v;
-  if (a.P > 1 && i < static_cast<size_t>(n.B) * a.P * 64) a.flags[i] = 0u;  // no flag of an earlier launch survives
 }
 
 hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
-  const size_t total = std::max(static_cast<size_t>(a.n.D + 1) * a.n.B * 2 * a.n.G, static_cast<size_t>(a.n.B) * a.P * 64);
+  const size_t total = static_cast<size_t>(a.n.D + 1) * a.n.B * 2 * a.n.G;
   hipLaunchKernelGGL(k_prefill_mailbox, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, a, t0);
   return hipGetLastError();
 }

@@ -95,7 +95,6 @@ struct SimArgs {
   const int32_t* wg_group;  // [P + 1] first group of every slice
   const int32_t* wg_chunk;  // [2][P + 1] first chunk of every slice: delay >= 2 part, delay-1 part
   uint64_t* mailbox;        // [D + 1][B][2G] tagged spike words: (step + 1) << 32 | 32 spike bits
-  uint32_t* flags;          // [B][P][64] step + 1 published by every slice (one flag per 256 bytes)
   uint32_t* status;         // set to nonzero when a wait times out
   int32_t P;
   int32_t ng_max;           // most groups in one slice
