@@ -366,6 +366,79 @@ def pin_matrix_form(oracle):
         assert np.array_equal(rd.spikes, sp) and np.array_equal(rd.V, V) and np.array_equal(rd.ref, ref)
 
 
+# ---------------------------------------------------------------------------
+# P13: brute force.  Every binary external input pattern of a 2- or 3-neuron
+# net over a few steps, run as one trial each, against a second transcription
+# of the six steps of the update (§2.1 with the readings above), written here
+# independently of the oracle: plain Python floats, one neuron at a time.
+# ---------------------------------------------------------------------------
+
+def _transcribed_run(n, syn, theta, leak, reset, refr, amp, x):
+    """x: [T][n] 0/1.  Returns (spikes [T][n], V [n], rho [n])."""
+    V = [float(reset[j]) for j in range(n)]
+    rho = [0] * n
+    history = []
+    for t in range(len(x)):
+        s_now = [0] * n
+        V_new = list(V)
+        rho_new = list(rho)
+        for j in range(n):
+            U = V[j]
+            if U > reset[j]:
+                U = max(U - leak[j], reset[j])
+            elif U < reset[j]:
+                U = min(U + leak[j], reset[j])
+            for (i, jj, w, d) in syn:
+                if jj == j and t - d >= 0 and history[t - d][i]:
+                    U += w
+            U += amp[j] * x[t][j]
+            fire = U > theta[j]
+            if rho[j] > 0:
+                s, rho_new[j] = 0, rho[j] - 1
+            else:
+                s, rho_new[j] = int(fire), 0
+            if s:
+                V_new[j], rho_new[j] = reset[j], int(refr[j])
+            else:
+                V_new[j] = U
+            s_now[j] = s
+        V, rho = V_new, rho_new
+        history.append(s_now)
+    return history, V, rho
+
+
+def pin_brute_force(oracle):
+    rng = np.random.default_rng(13)
+    cases = [(2, 6, 1), (2, 6, 2), (3, 4, 1), (3, 4, 2), (2, 5, 2), (3, 4, 2)]
+    for c, (n, T, D) in enumerate(cases):
+        m = int(rng.integers(1, 6))
+        pre = rng.integers(0, n, m)
+        post = rng.integers(0, n, m)          # self-loops and duplicates allowed
+        w = rng.choice([-1.0, -0.5, 0.25, 0.5, 1.0, 1.5], m)
+        d = rng.integers(1, D + 1, m)
+        theta = rng.choice([0.0, 0.5, 1.0], n)
+        leak = rng.choice([0.0, 0.25, np.inf], n)
+        reset = rng.choice([-0.5, 0.0, 0.25], n)
+        theta = np.maximum(theta, reset)
+        refr = rng.integers(0, 3, n)
+        amp = rng.choice([0.5, 1.0, 2.0], n)
+        B = 1 << (n * T)
+        codes = np.arange(B, dtype=np.int64)
+        ext = ((codes[:, None] >> np.arange(n * T)) & 1).astype(np.uint8).reshape(B, T, n)
+        net = Network("brute", n, B, D, T, theta.astype(np.float32), leak.astype(np.float32),
+                      reset.astype(np.float32), refr.astype(np.uint8), amp.astype(np.float32),
+                      pre.astype(np.int32), post.astype(np.int32), w.astype(np.float32),
+                      d.astype(np.uint8), ext)
+        res = oracle.run_sparse(net)
+        syn = list(zip(pre.tolist(), post.tolist(), w.tolist(), d.tolist()))
+        for b in range(B):
+            sp, V, rho = _transcribed_run(n, syn, theta.tolist(), leak.tolist(), reset.tolist(),
+                                          refr.tolist(), amp.tolist(), ext[b].tolist())
+            assert np.array_equal(res.spikes[b], np.asarray(sp, np.uint8)), f"brute force case {c} pattern {b}"
+            assert np.array_equal(res.V[b], np.asarray(V)) and np.array_equal(res.ref[b], np.asarray(rho)), \
+                f"brute force state, case {c} pattern {b}"
+
+
 ALL_PINS = [pin_constant_drive, pin_leak_relaxation, pin_single_delay, pin_chain, pin_loop,
             pin_refractory, pin_proxy_equivalence, pin_rest, pin_permutation, pin_trials,
-            pin_time_shift, pin_disjoint_union, pin_matrix_form]
+            pin_time_shift, pin_disjoint_union, pin_matrix_form, pin_brute_force]
