@@ -14,6 +14,9 @@ device memory.  Workloads:
                           T = 1000, matrix cores
   uneven_batch            512 independent nets, N 50..5000, T = 500: one
                           batched persistent launch vs one run per net
+  bptt                    surrogate-gradient training step of a recurrent
+                          layer: N = 2048, 256 inputs, 128 trials, T = 200
+                          (forward + backward through time), FP32 matrix cores
 
 Prints one JSON line.
 """
@@ -32,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix cores, TFLOP/s
+FP32_PEAK_TFLOPS = 157.3    # MI355X dense fp32 (matrix cores), TFLOP/s
 
 
 def events_of(raster_btn: np.ndarray, out_degree: np.ndarray) -> int:
@@ -222,13 +226,78 @@ def bench_batch(args):
     return out
 
 
+def bench_bptt(args):
+    """One training step (forward with checkpoints + backward through time)
+    of the recurrent LIF layer per benchmark step."""
+    import torch
+    from paper_2305_02510_amd import workloads as wl
+    from paper_2305_02510_amd.bptt import spike_counts
+    prob = wl.bptt_problem(5)
+    T, B, Nin = prob.x.shape
+    N = prob.W_rec.shape[0]
+    Wr = torch.tensor(prob.W_rec, device="cuda", requires_grad=True)
+    Wi = torch.tensor(prob.W_in, device="cuda", requires_grad=True)
+    x = torch.tensor(prob.x, dtype=torch.float32, device="cuda")
+    tgt = torch.tensor(prob.target, device="cuda")
+    out_counts = {}
+
+    def step():
+        Wr.grad = None
+        Wi.grad = None
+        counts = spike_counts(Wr, Wi, x, prob.theta, prob.leak, prob.reset, prob.slope, prob.checkpoint)
+        loss = ((counts / T - tgt) ** 2).mean()
+        loss.backward()
+        out_counts["c"] = counts
+
+    stream = torch.cuda.current_stream()
+    ms, wall = timed(step, stream, args.warmup, args.steps)
+    counts = out_counts["c"].detach().cpu().numpy()
+    # algorithmic flops per training step: forward [s | x] W_cat, backward
+    # g W_rec^T and the weight gradient [s | x]^T g, every step and trial
+    flops = 2.0 * T * B * N * (2 * (N + Nin) + N)
+    achieved = flops / (ms / 1e3) / 1e12
+    out = {"value": 1e3 / ms, "ms_per_step": ms, "wall": wall, "path": "bptt",
+           "mean_firing_rate": float(counts.mean() / T),
+           "neuron_updates_per_s": B * N * T / (ms / 1e3), "config": {
+               "workload": f"bptt: recurrent N={N}, inputs={Nin}, trials={B}, T={T}, checkpoint every "
+                           f"{prob.checkpoint} steps, dense delay-1 weights", "trials": B, "time_steps_per_run": T}}
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": None,
+                       "kernel": "k_bptt_forward + k_bptt_backward + k_bptt_wgrad (whole step)",
+                       "flops_per_step": flops}
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.default()
+        picks = [0]
+        c0 = time.perf_counter()
+        ref = orc.bptt(prob.W_rec, prob.W_in, prob.x[:, picks], prob.target, prob.theta, prob.leak, prob.reset,
+                       prob.slope)
+        csec = time.perf_counter() - c0
+        out["cpu_baseline"] = {
+            "value": round(len(picks) / B / csec, 6), "unit": "training steps/s", "cores": cpu_threads_used(),
+            "kind": "oracle", "sample": f"{len(picks)} of {B} trials (a step's cost is linear in trials), "
+                                        f"all {T} steps: {csec:.2f} s single-threaded"}
+        out["parity_bit_exact"] = None
+        Wr.grad = None
+        Wi.grad = None
+        c = spike_counts(Wr, Wi, x[:, picks].contiguous(), prob.theta, prob.leak, prob.reset, prob.slope,
+                         prob.checkpoint)
+        ((c / T - tgt) ** 2).mean().backward()
+        g = Wr.grad.double().cpu().numpy()
+        rel = float(np.linalg.norm(g - ref.dW_rec) / np.linalg.norm(ref.dW_rec))
+        out["parity_counts_exact"] = bool(np.array_equal(c.detach().cpu().numpy(), ref.counts))
+        out["parity_grad_rel_err"] = rel
+        out["parity_sample"] = f"trials {picks}: dW_rec relative Frobenius error vs the FP64 oracle"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_sparse",
-                    choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch"])
+                    choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch", "bptt"])
     ap.add_argument("--path", default="auto")
     ap.add_argument("--cpu-trials", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -254,6 +323,20 @@ def main():
     from paper_2305_02510_amd import workloads as wl
     torch.cuda.set_device(0)
 
+    if args.workload == "bptt":
+        r = bench_bptt(args)
+        out = {
+            "metric": "training steps/sec", "value": round(r["value"], 4), "unit": "training steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (seeded dense recurrent weights and Bernoulli input spikes)",
+            "config": r["config"], "neuron_updates_per_s": round(r["neuron_updates_per_s"], 1),
+            "mean_firing_rate": round(r["mean_firing_rate"], 5), "roofline": r["roofline"],
+            "cpu_baseline": r.get("cpu_baseline"), "parity_counts_exact": r.get("parity_counts_exact"),
+            "parity_grad_rel_err": r.get("parity_grad_rel_err"), "parity_sample": r.get("parity_sample"),
+            "wall_s_timed": round(r["wall"], 4)}
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "uneven_batch":
         r = bench_batch(args)
         desc = (f"uneven_batch: {r['nets']} independent nets, N log-uniform 50..5000 (total {r['total_neurons']}), "

@@ -51,11 +51,11 @@ struct sn_net {
   // synapse buffers (replaced by a new load)
   void* recs = nullptr;
   void* gptr = nullptr;
-  void* chunks = nullptr;
+  void* gsplit = nullptr;
   // persistent-kernel plans: one slice (SMALL) and several slices (PERSIST)
   struct DevPlan {
     SlicePlan host;
-    void* wg = nullptr;  // [2][P + 1] int32: wg_group then wg_chunk
+    void* wg = nullptr;  // [P + 1] int32: first group of every slice
     bool ok = false;
   };
   DevPlan small, persist;
@@ -157,18 +157,17 @@ sn_status ensure_rows(sn_net* n, int64_t rows) {
 // false if the slice plan cannot run at all.
 bool fit_plan(const DevNet& d, SlicePlan& p) {
   if (p.P < 1 || sim_npt(p.ng_max, p.max_recs) > 8) return false;
+  const int nwave = sim_threads(p.ng_max, p.max_recs) / kGroup;
   // the spike ring goes to LDS whenever it fits beside the accumulators: a
-  // global ring costs a device-scope load per synapse; chunk headers go to
-  // LDS whenever they fit (they are 1/32 of the record bytes)
-  const bool ring_fits = sim_lds_bytes(d, p.ng_max, 0, 0, false, true, false) <= 96 * 1024;
-  const bool opts[8][3] = {{true, true, true},   {true, true, false},  {false, true, true},  {false, true, false},
-                           {true, false, true},  {true, false, false}, {false, false, true}, {false, false, false}};
+  // global ring costs a device-scope load per synapse
+  const bool ring_fits = sim_lds_bytes(d, p.ng_max, 0, nwave, false, true) <= 96 * 1024;
+  // (records in LDS, ring in LDS), preferred first
+  const bool opts[4][2] = {{true, true}, {false, true}, {true, false}, {false, false}};
   for (const auto& o : opts) {
     if (ring_fits && !o[1]) continue;
-    if (sim_lds_bytes(d, p.ng_max, p.max_recs, p.max_chunks, o[0], o[1], o[2]) <= lds_limit()) {
+    if (sim_lds_bytes(d, p.ng_max, p.max_recs, nwave, o[0], o[1]) <= lds_limit()) {
       p.recs_lds = o[0];
       p.ring_lds = o[1];
-      p.hdr_lds = o[2];
       return true;
     }
   }
@@ -196,8 +195,7 @@ sn_status upload_plan(sn_net* n, sn_net::DevPlan& dp, const SlicePlan& p) {
   dp.host = p;
   dp.ok = p.P > 0;
   if (!dp.ok) return SN_OK;
-  std::vector<int32_t> buf(p.wg_group);
-  buf.insert(buf.end(), p.wg_chunk.begin(), p.wg_chunk.end());
+  const std::vector<int32_t>& buf = p.wg_group;
   dp.wg = dev_alloc(n, buf.size() * sizeof(int32_t));
   if (!dp.wg) return fail(SN_ENOMEM, "cannot allocate slice tables");
   SN_HIP(n, hipMemcpyAsync(dp.wg, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
@@ -209,14 +207,11 @@ SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
   SimArgs a{};
   a.n = n->d;
   a.wg_group = static_cast<const int32_t*>(dp.wg);
-  a.wg_chunk = static_cast<const int32_t*>(dp.wg) + dp.host.P + 1;
   a.mailbox = n->mailbox;
   a.status = n->status;
   a.P = dp.host.P;
   a.ng_max = dp.host.ng_max;
   a.max_recs = dp.host.max_recs;
-  a.max_chunks = dp.host.max_chunks;
-  a.hdr_lds = dp.host.hdr_lds ? 1 : 0;
   return a;
 }
 
@@ -379,7 +374,7 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     if (n->poisoned) return fail(SN_ESTATE, "network %d is poisoned", k);
     if (!n->synapses_loaded) return fail(SN_ESTATE, "network %d has no synapses", k);
     if (n->device != v[0]->device) return fail(SN_EINVAL, "networks are on different devices");
-    if (batch_lds_bytes(n->d, 0, 0) > 96 * 1024) return fail(SN_ERANGE, "network %d: spike ring too large for a batch", k);
+    if (batch_lds_bytes(n->d, 1) > 96 * 1024) return fail(SN_ERANGE, "network %d: spike ring too large for a batch", k);
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v[0]->device) != hipSuccess) {
@@ -398,12 +393,9 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
   bt->nets = v;
   bt->stream = v[0]->stream;
   // workgroups resident at once, for the largest LDS any network needs
-  // LDS per workgroup: the largest spike ring + accumulators, plus room for
-  // the chunk headers of a slice (headers that do not fit stay in global memory)
+  // (its spike ring, accumulators, partial sums and group offsets)
   size_t lds = 0;
-  for (sn_net* n : v) lds = std::max(lds, batch_lds_bytes(n->d, std::min<int32_t>(n->d.G, kBatchMaxGroups), 0));
-  lds = std::min<size_t>(lds + 16 * 1024, 160 * 1024 - 64);
-  const size_t lds_budget = lds;
+  for (sn_net* n : v) lds = std::max(lds, batch_lds_bytes(n->d, std::min<int32_t>(n->d.G, kBatchMaxGroups)));
   const int per_cu = batch_blocks_per_cu(lds);
   if (per_cu < 1) {
     delete bt;
@@ -440,8 +432,6 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     }
     bt->plan_off[k] = tables.size();
     tables.insert(tables.end(), p.wg_group.begin(), p.wg_group.end());
-    tables.insert(tables.end(), p.wg_chunk.begin(), p.wg_chunk.end());
-    p.hdr_lds = batch_lds_bytes(n->d, p.ng_max, p.max_chunks) <= lds_budget;
     bt->plans[k] = std::move(p);
   }
   bt->lds = lds;
@@ -515,14 +505,11 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
     SimArgs a{};
     a.n = n->d;
     a.wg_group = tables + bt->plan_off[k];
-    a.wg_chunk = tables + bt->plan_off[k] + p.P + 1;
     a.mailbox = n->mailbox;
     a.status = n->status;
     a.P = p.P;
     a.ng_max = p.ng_max;
     a.max_recs = p.max_recs;
-    a.max_chunks = p.max_chunks;
-    a.hdr_lds = p.hdr_lds ? 1 : 0;
     bt->descs[k].team = a;
     bt->descs[k].single = a;
     if (p.P > 1) {
@@ -696,30 +683,29 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay);
   void* recs = dev_alloc(n, L.recs.size() * sizeof(Rec));
   void* gptr = dev_alloc(n, L.gptr.size() * sizeof(int32_t));
-  void* chunks = dev_alloc(n, L.chunks.size() * sizeof(uint2));
-  if (!recs || !gptr || !chunks) {
+  void* gsplit = dev_alloc(n, L.gsplit.size() * sizeof(int32_t));
+  if (!recs || !gptr || !gsplit) {
     dev_free(n, recs);
     dev_free(n, gptr);
-    dev_free(n, chunks);
+    dev_free(n, gsplit);
     return fail(SN_ENOMEM, "cannot allocate synapse records");
   }
   // the previous buffers may be in use by queued work
   SN_HIP(n, hipStreamSynchronize(n->stream));
   dev_free(n, n->recs);
   dev_free(n, n->gptr);
-  dev_free(n, n->chunks);
+  dev_free(n, n->gsplit);
   n->recs = recs;
   n->gptr = gptr;
-  n->chunks = chunks;
+  n->gsplit = gsplit;
   if (!L.recs.empty())
     SN_HIP(n, hipMemcpyAsync(recs, L.recs.data(), L.recs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipMemcpyAsync(gptr, L.gptr.data(), L.gptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
-  if (!L.chunks.empty())
-    SN_HIP(n, hipMemcpyAsync(chunks, L.chunks.data(), L.chunks.size() * sizeof(uint2), hipMemcpyHostToDevice, n->stream));
+  SN_HIP(n, hipMemcpyAsync(gsplit, L.gsplit.data(), L.gsplit.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipStreamSynchronize(n->stream));  // host vectors die at return
   n->d.recs = static_cast<const Rec*>(recs);
   n->d.gptr = static_cast<const int32_t*>(gptr);
-  n->d.chunks = static_cast<const uint2*>(chunks);
+  n->d.gsplit = static_cast<const int32_t*>(gsplit);
   {
     HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
     void* orecs = dev_alloc(n, H.orecs.size() * sizeof(Rec));
@@ -739,7 +725,6 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     SN_HIP(n, hipStreamSynchronize(n->stream));
   }
   n->d.nnz = nnz;
-  n->d.nchunks = static_cast<int32_t>(L.chunks.size());
   n->synapses_loaded = true;
   dev_free(n, n->wt);
   n->wt = nullptr;
@@ -999,7 +984,7 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, const_cast<uint64_t*>(n->d.ext));
   dev_free(n, n->recs);
   dev_free(n, n->gptr);
-  dev_free(n, n->chunks);
+  dev_free(n, n->gsplit);
   dev_free(n, n->small.wg);
   dev_free(n, n->persist.wg);
   dev_free(n, n->wt);

@@ -18,23 +18,30 @@ namespace snmi {
 // of D + 1 bit rows (slot t mod (D+1) holds step t; step t reads the slots of
 // t - d, d = 1..D, never its own), in LDS when it fits.
 //
+// Delivery.  Records in lane-owned rows (lane l holds a synapse of post l)
+// add into a register of their lane; only overflow records of high
+// in-degree posts use LDS atomics.  How the waves share the groups is one of
+// three modes (kModeSlot, kModeOwn, kModeRange) chosen per slice.
+//
 // Spike exchange.  Every step each workgroup also publishes its spike words,
 // 32 spikes per 64-bit word tagged with the step: (t + 1) << 32 | bits, stored
 // with one device-scope relaxed atomic in the mailbox ring [D+1][B][2G].
 // Because tag and data share one atomic location, a reader that sees tag
 // t + 1 sees that step's bits; no cache writeback or invalidate is needed.
 // A workgroup first delivers its delay >= 2 synapses (history it already
-// holds), then reads row t - 1, waiting on any word whose tag is not yet
-// t, then delivers its delay-1 synapses.  A slice runs at most one step ahead of the slowest,
-// so a slot is never rewritten before every reader is done with it.  Without
-// an LDS ring the bits are read from the mailbox ring itself.  Every wait is
-// bounded: after kSpinLimit polls the workgroup records a timeout in *status
-// and all its waves exit; slices waiting on it then time out the same way.
+// holds), then reads row t - 1, waiting on any word whose tag is not yet t,
+// then delivers its delay-1 synapses.  A slice runs at most one step ahead
+// of the slowest, so a slot is never rewritten before every reader is done
+// with it.  Without an LDS ring the bits are read from the mailbox ring
+// itself.  Every wait is bounded: after kSpinLimit polls the workgroup
+// records a timeout in *status and all its waves exit; slices waiting on it
+// then time out the same way.
 //
 // Thread tid owns the neurons of local groups wave + k * nwave (k < NPT), so
 // the ballot of a wave is the spike word of one group.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kMaxWaves = 16;  // waves of the largest workgroup (1024 threads)
 
 __device__ __forceinline__ uint64_t load_dev(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -44,80 +51,232 @@ __device__ __forceinline__ void store_dev(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Delivers the chunks [c, c_end) of the calling wave's share (every nwave-th
-// chunk): four independent record / bit / accumulate chains per lane.  When
-// records stream from global memory, the next chunk's records are loaded
-// while the current one is processed.
-// Header of chunk c: from LDS (lhdr[c - hoff]) when staged there, else global.
-struct Hdr {
-  const uint2* lhdr;
-  int hoff;
-  bool in_lds;
-};
+// Meta word of a record staged in LDS next to an LDS spike ring: bits 0-15
+// the ring offset (Dr - d) * W32 + pre / 32 of the source word relative to
+// the current row (row t - d = cur - d mod Dr), bits 16-20 the source bit
+// pre % 32, bits 26-31 the post-neuron in its group (as in global records).
+// A ring held in LDS has Dr * W32 < 2^16 words, so the offset fits.
+__device__ __forceinline__ uint32_t lds_meta(uint32_t m, int Dr, int W32) {
+  const uint32_t d = ((m >> 20) & 63u) + 1u;
+  const uint32_t pre = m & 0xFFFFFu;
+  return ((static_cast<uint32_t>(Dr) - d) * static_cast<uint32_t>(W32) + (pre >> 5)) | ((pre & 31u) << 16) |
+         (m & 0xFC000000u);
+}
 
+// LDS accumulator rows per group: two buffers (by step parity) when several
+// waves deliver into one group, so a fast wave of step t + 1 never adds into
+// the row the updating wave is still reading for step t.
+__host__ __device__ __forceinline__ int acc_rows(int ng_max, int nwave) {
+  return ng_max < nwave ? 2 * ng_max : ng_max;
+}
+
+// Records [k, k + 4 * 64) of the calling lane's chunk (four, 64 apart);
+// valid[u] is false past `end`.  LDS loads are issued unconditionally with
+// the index clamped into the chunk, so the four are in flight together.
 template <bool RECS_LDS>
-__device__ __forceinline__ void load_chunk(const DevNet& n, const Rec* lrec, const Hdr& hdr, int c, int lane, int r0,
-                                           Rec (&rc)[4], int& lg_g, int& cnt) {
-  const uint2 ch = hdr.in_lds ? hdr.lhdr[c - hdr.hoff] : n.chunks[c];
-  const int start = static_cast<int>(ch.x);
-  lg_g = static_cast<int>(ch.y & 0xFFFFFu);
-  cnt = static_cast<int>(ch.y >> 20);
+__device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int start, int end, int lane, int r0,
+                                          Rec (&rc)[4], bool (&valid)[4]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int i = lane + 64 * u;
-    rc[u] = Rec{0.f, 0u};
-    if (i < cnt) rc[u] = RECS_LDS ? lrec[start - r0 + i] : n.recs[start + i];
+    const int k = start + lane + 64 * u;
+    valid[u] = k < end;
+    if (RECS_LDS) {
+      rc[u] = lrec[(k < end ? k : start) - r0];
+    } else {
+      rc[u] = Rec{0.f, 0u};
+      if (k < end) rc[u] = n.recs[k];
+    }
   }
 }
 
-// Chunk headers come from LDS when the slice's headers were staged there, so
-// a record load never waits on a dependent global load.
+// How the waves of a workgroup share the delivery of its ng groups:
+//   kModeSlot   ng < nwave: team q of m = nwave / ng waves delivers group q,
+//               member i the chunks i, i + m, ...; partial sums go to LDS
+//               slots read by the updating wave;
+//   kModeOwn    wave w delivers the groups w, w + nwave, ... (those it also
+//               updates), used when that balances: ng a multiple of nwave or
+//               at least 4 nwave;
+//   kModeRange  otherwise: the groups' chunks are cut into nwave contiguous
+//               ranges; a group inside one range is added to its accumulator
+//               row directly, a group split between ranges atomically.
+constexpr int kModeSlot = 0, kModeOwn = 1, kModeRange = 2;
+
+// The four records of one chunk held by a lane: source bits from the ring
+// (or the mailbox), own-post weights into *sum, other posts atomically.
 template <bool RECS_LDS, bool RING_LDS>
-__device__ __forceinline__ void deliver(const DevNet& n, const Rec* lrec, const Hdr& hdr, const uint32_t* ring,
-                                        const uint64_t* mring, float* acc, int c, int c_end, int nwave,
-                                        int lane, int g0, int r0, int t, int cur, int Dr, int W32) {
-  if (c >= c_end) return;
-  Rec rc[4];
-  int g = 0, cnt = 0;
-  load_chunk<RECS_LDS>(n, lrec, hdr, c, lane, r0, rc, g, cnt);
-  for (; c < c_end; c += nwave) {
-    Rec nx[4];
-    int ng = 0, ncnt = 0;
-    if (!RECS_LDS && c + nwave < c_end) load_chunk<RECS_LDS>(n, lrec, hdr, c + nwave, lane, r0, nx, ng, ncnt);
-    uint32_t bit[4];
+__device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[4], const bool (&valid)[4],
+                                              const uint32_t* ring, const uint64_t* mring, float* acc_g, float& sum,
+                                              int lane, int t, int cur, int Dr, int W32, uint32_t curW, uint32_t DrW) {
+  uint32_t bit[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t m = rc[u].meta;
-      const int d = static_cast<int>((m >> 20) & 63u) + 1;
-      const uint32_t pre = m & 0xFFFFFu;
+  for (int u = 0; u < 4; ++u) {
+    const uint32_t mt = rc[u].meta;
+    if (RING_LDS && RECS_LDS) {
+      // staged records carry their ring offset (see lds_meta): the row of
+      // step t - d is cur - d modulo Dr, i.e. one add and a wrap.  A clamped
+      // record (past the end) is a valid record, so the read stays inside
+      // the ring; masking arithmetically keeps the four reads unconditional
+      // and in flight together.  Rows of steps before 0 are zero in the
+      // ring, so no test of t - d is needed.
+      uint32_t adr = curW + (mt & 0xFFFFu);
+      adr = min(adr, adr - DrW);
+      bit[u] = (ring[adr] >> ((mt >> 16) & 31u)) & static_cast<uint32_t>(valid[u]);
+      continue;
+    }
+    const int d = static_cast<int>((mt >> 20) & 63u) + 1;
+    const uint32_t pre = mt & 0xFFFFFu;
+    int slot = cur - d;
+    if (slot < 0) slot += Dr;
+    if (RING_LDS) {
+      bit[u] = (ring[slot * W32 + (pre >> 5)] >> (pre & 31u)) & static_cast<uint32_t>(valid[u]);
+    } else {
       bit[u] = 0u;
-      if (lane + 64 * u < cnt && t - d >= 0) {
-        int slot = cur - d;
-        if (slot < 0) slot += Dr;
-        const uint32_t word = RING_LDS ? ring[slot * W32 + (pre >> 5)]
-                                       : static_cast<uint32_t>(load_dev(mring + static_cast<size_t>(slot) * n.B * W32 + (pre >> 5)));
+      if (valid[u] && t - d >= 0) {
+        const uint32_t word =
+            static_cast<uint32_t>(load_dev(mring + static_cast<size_t>(slot) * n.B * W32 + (pre >> 5)));
         bit[u] = (word >> (pre & 31u)) & 1u;
       }
     }
-    const int lg = g - g0;
+  }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (bit[u]) atomicAdd(&acc[lg * kGroup + (rc[u].meta >> 26)], rc[u].w);
-    }
-    if (c + nwave < c_end) {
-      if (RECS_LDS) {
-        load_chunk<RECS_LDS>(n, lrec, hdr, c + nwave, lane, r0, rc, g, cnt);
-      } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) rc[u] = nx[u];
-        g = ng;
-        cnt = ncnt;
-      }
-    }
+  for (int u = 0; u < 4; ++u) {
+    const uint32_t post = rc[u].meta >> 26;
+    sum += (bit[u] && post == static_cast<uint32_t>(lane)) ? rc[u].w : 0.f;
+    if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], rc[u].w);
   }
 }
 
-template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI>
+// Slot mode: the chunks member, member + m, ... of the records [beg, end)
+// of one group part.  Returns the lane's own-post sum.
+template <bool RECS_LDS, bool RING_LDS>
+__device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec, const uint32_t* ring,
+                                               const uint64_t* mring, float* acc_g, int beg, int end, int member,
+                                               int m, int lane, int r0, int t, int cur, int Dr, int W32) {
+  float sum = 0.f;
+  int start = beg + member * kChunk;
+  if (start >= end) return sum;
+  const uint32_t curW = static_cast<uint32_t>(cur * W32);
+  const uint32_t DrW = static_cast<uint32_t>(Dr * W32);
+  const int stride = m * kChunk;
+  Rec rc[4];
+  bool valid[4];
+  load_recs<RECS_LDS>(n, lrec, start, end, lane, r0, rc, valid);
+  for (; start < end; start += stride) {
+    Rec nx[4];
+    bool nvalid[4];
+    if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
+    deliver_chunk<RECS_LDS, RING_LDS>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    if (start + stride < end) {
+      if (RECS_LDS) {
+        load_recs<RECS_LDS>(n, lrec, start + stride, end, lane, r0, rc, valid);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rc[u] = nx[u];
+          valid[u] = nvalid[u];
+        }
+      }
+    }
+  }
+  return sum;
+}
+
+// One part of the delivery (delay >= 2 or delay 1) as a walk over chunks.
+// cs[lg] .. cs[lg + 1] are the part's chunks of group lg, bp[lg] / ep[lg]
+// its first / past-last record.  The walk starts at chunk c of group lg and
+// steps by cstride inside a group; at a group's end (or at chunk hi) it
+// moves by gstep groups (0: stop).  A lane sums the records of its own post
+// (lane-owned rows) in a register and flushes the sum when the group
+// changes: Slot mode returns it, Own and Range modes add it into acc[lg]
+// (Range: atomically unless the whole group lies in [lo, hi)).  Records of
+// other posts (overflow) are added into acc[lg][post] atomically.  Records
+// in global memory are prefetched one chunk ahead, across group changes.
+template <bool RECS_LDS, bool RING_LDS>
+__device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const uint32_t* ring,
+                                         const uint64_t* mring, float* acc, const int* cs, const int* bp,
+                                         const int* ep, int ng, int lg, int c, int cstride, int gstep, int lo, int hi,
+                                         int mode, int lane, int r0, int t, int cur, int Dr, int W32) {
+  float ret = 0.f;
+  // the first item: skip to a group with chunks left
+  auto item_end = [&](int g) { return mode == kModeRange ? min(cs[g + 1], hi) : cs[g + 1]; };
+  if (mode == kModeRange ? c >= hi : c >= item_end(lg)) {
+    if (mode != kModeOwn) return ret;
+    while (lg < ng && cs[lg] == cs[lg + 1]) lg += gstep;
+    if (lg >= ng) return ret;
+    c = cs[lg];
+  }
+  const uint32_t curW = static_cast<uint32_t>(cur * W32);
+  const uint32_t DrW = static_cast<uint32_t>(Dr * W32);
+  // the current group's records, first chunk and chunk bound (re-read from
+  // LDS only when the walk moves to another group)
+  int beg = bp[lg], end = ep[lg], c0 = cs[lg], cend = item_end(lg);
+  Rec rc[4];
+  bool valid[4];
+  load_recs<RECS_LDS>(n, lrec, beg + (c - c0) * kChunk, end, lane, r0, rc, valid);
+  float sum = 0.f;
+  for (;;) {
+    // the next item
+    int nlg = lg, nc = c + cstride;
+    bool more = true;
+    if (nc >= cend) {
+      if (mode == kModeSlot) {
+        more = false;
+      } else if (mode == kModeRange) {
+        more = nc < hi;
+        nlg = lg + 1;
+        while (more && cs[nlg + 1] <= nc) ++nlg;  // skip groups without chunks
+      } else {
+        nlg = lg + gstep;
+        while (nlg < ng && cs[nlg] == cs[nlg + 1]) nlg += gstep;
+        more = nlg < ng;
+        nc = more ? cs[nlg] : nc;
+      }
+    }
+    int nbeg = beg, nend = end, nc0 = c0, ncend = cend;
+    if (nlg != lg && more) {
+      nbeg = bp[nlg];
+      nend = ep[nlg];
+      nc0 = cs[nlg];
+      ncend = item_end(nlg);
+    }
+    Rec nx[4];
+    bool nvalid[4];
+    if (!RECS_LDS && more) load_recs<RECS_LDS>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, nx, nvalid);
+    float* acc_g = acc + lg * kGroup;
+    deliver_chunk<RECS_LDS, RING_LDS>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    if (!more || nlg != lg) {  // flush the group's register sum (uniform)
+      if (mode == kModeSlot) {
+        ret = sum;
+      } else if (mode == kModeOwn || (cs[lg] >= lo && cs[lg + 1] <= hi)) {
+        acc_g[lane] += sum;  // this wave is the group's only contributor in this part
+      } else {
+        atomicAdd(&acc_g[lane], sum);
+      }
+      sum = 0.f;
+    }
+    if (!more) break;
+    if (RECS_LDS) {
+      load_recs<RECS_LDS>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, rc, valid);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rc[u] = nx[u];
+        valid[u] = nvalid[u];
+      }
+    }
+    lg = nlg;
+    c = nc;
+    beg = nbeg;
+    end = nend;
+    c0 = nc0;
+    cend = ncend;
+  }
+  return ret;
+}
+
+// PARAMS_LDS: neuron parameters live in LDS instead of registers (the batch
+// kernel, whose occupancy is bound by registers, not LDS).
+template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI, bool PARAMS_LDS = false>
 __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0, int steps, unsigned char* smem,
                                          int& abort_flag) {
   const DevNet& n = a.n;
@@ -130,35 +289,57 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
   const int W32 = 2 * n.G;
   const int g0 = a.wg_group[w];
   const int ng = a.wg_group[w + 1] - g0;
-  const int cA0 = a.wg_chunk[w], cA1 = a.wg_chunk[w + 1];
-  const int cB0 = a.wg_chunk[a.P + 1 + w], cB1 = a.wg_chunk[a.P + 1 + w + 1];
   const int r0 = n.gptr[g0];
   const int nrec = n.gptr[g0 + ng] - r0;
   const bool use_mail = MULTI || !RING_LDS;
+  // delivery mode (see kModeSlot) and accumulator buffers
+  const int m = ng < nwave ? nwave / ng : 1;
+  const int team = wave / m;
+  const int member = wave - team * m;
+  const int mode = (ng < nwave && 4 * m * ng >= 3 * nwave) ? kModeSlot
+                   : (ng >= nwave && (ng % nwave == 0 || ng >= 4 * nwave)) ? kModeOwn : kModeRange;
+  const int nacc = acc_rows(a.ng_max, nwave) > a.ng_max ? 2 : 1;
+  // another wave may add into a group's row while its updater reads it, so
+  // the step ends with a barrier unless the rows alternate by step parity
+  const bool end_barrier = mode != kModeOwn && nacc == 1;
   // mailbox ring of this trial: slot s at mring + s * B * W32
   uint64_t* mring = a.mailbox + static_cast<size_t>(b) * W32;
 
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);
-  float* acc = reinterpret_cast<float*>(ring + (RING_LDS ? Dr * W32 : 0));
-  uint2* lhdr = reinterpret_cast<uint2*>(acc + a.ng_max * kGroup);  // offsets are multiples of 8 bytes
-  Rec* lrec = reinterpret_cast<Rec*>(lhdr + (a.hdr_lds ? a.max_chunks : 0));
-  // chunk headers of both parts: part A at lhdr[0 .. nA), part B after it
-  const int nA = cA1 - cA0;
-  const Hdr hA{lhdr, cA0, a.hdr_lds != 0};
-  const Hdr hB{lhdr + nA, cB0, a.hdr_lds != 0};
+  float* acc = reinterpret_cast<float*>(ring + (RING_LDS ? Dr * W32 : 0));  // [nacc][ng_max][64]
+  float* part = acc + acc_rows(a.ng_max, nwave) * kGroup;                    // [kMaxWaves][64]
+  int* gsp = reinterpret_cast<int*>(part + kMaxWaves * kGroup);  // [ng + 1] starts, [ng] splits
+  int* csA = gsp + 2 * a.ng_max + 1;                              // [ng + 1] chunk offsets, delay >= 2
+  int* csB = csA + a.ng_max + 1;                                  // [ng + 1] chunk offsets, delay 1
+  float* prm = reinterpret_cast<float*>(csB + a.ng_max + 2);      // PARAMS_LDS: [5][ng_max][64]
+  Rec* lrec = reinterpret_cast<Rec*>(prm + (PARAMS_LDS ? 5 * a.ng_max * kGroup : 0));  // 8-byte aligned
 
   if (tid == 0) abort_flag = 0;
   __syncthreads();
   if (RING_LDS) {
     for (int i = tid; i < Dr * W32; i += nthr) ring[i] = 0u;
   }
-  for (int i = tid; i < ng * kGroup; i += nthr) acc[i] = 0.f;
-  if (RECS_LDS) {
-    for (int i = tid; i < nrec; i += nthr) lrec[i] = n.recs[r0 + i];
+  for (int i = tid; i < acc_rows(a.ng_max, nwave) * kGroup; i += nthr) acc[i] = 0.f;
+  for (int i = tid; i <= ng; i += nthr) gsp[i] = n.gptr[g0 + i];
+  for (int i = tid; i < ng; i += nthr) gsp[ng + 1 + i] = n.gsplit[g0 + i];
+  if (tid == 0) {  // chunk offsets of both parts (after the loads above land)
+    int ca = 0, cb = 0;
+    for (int i = 0; i < ng; ++i) {
+      const int s0 = n.gptr[g0 + i], s1 = n.gsplit[g0 + i], s2 = n.gptr[g0 + i + 1];
+      csA[i] = ca;
+      csB[i] = cb;
+      ca += (s1 - s0 + kChunk - 1) / kChunk;
+      cb += (s2 - s1 + kChunk - 1) / kChunk;
+    }
+    csA[ng] = ca;
+    csB[ng] = cb;
   }
-  if (a.hdr_lds) {
-    for (int i = tid; i < nA; i += nthr) lhdr[i] = n.chunks[cA0 + i];
-    for (int i = tid; i < cB1 - cB0; i += nthr) lhdr[nA + i] = n.chunks[cB0 + i];
+  if (RECS_LDS) {
+    for (int i = tid; i < nrec; i += nthr) {
+      Rec r = n.recs[r0 + i];
+      if (RING_LDS) r.meta = lds_meta(r.meta, Dr, W32);
+      lrec[i] = r;
+    }
   }
   __syncthreads();
   if (RING_LDS) {  // history of the steps before t0 (rows < 0 stay zero)
@@ -176,35 +357,72 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     }
   }
 
-  float V[NPT], th[NPT], lam[NPT], rs[NPT], amp[NPT];
-  int ref[NPT], R[NPT];
-  uint64_t ew[NPT];
+  // where this wave's walk over each part starts (see deliver)
+  int wlg[2], wc[2], wlo[2], whi[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int* cs = x == 0 ? csA : csB;
+    const int q = cs[ng];
+    wlo[x] = 0;
+    whi[x] = q;
+    if (mode == kModeSlot) {
+      wlg[x] = team < ng ? team : ng;
+      wc[x] = team < ng ? cs[team] + member : q;
+    } else if (mode == kModeOwn) {
+      wlg[x] = wave;
+      wc[x] = wave < ng ? cs[wave] : q;
+    } else {
+      wlo[x] = static_cast<int>(static_cast<int64_t>(q) * wave / nwave);
+      whi[x] = static_cast<int>(static_cast<int64_t>(q) * (wave + 1) / nwave);
+      int g = 0;
+      while (g < ng && cs[g + 1] <= wlo[x]) ++g;
+      wlg[x] = g;
+      wc[x] = wlo[x];
+    }
+  }
+  constexpr int NP = PARAMS_LDS ? 1 : NPT;  // parameter registers
+  float V[NPT], th[NP], lam[NP], rs[NP], amp[NP];
+  int ref[NPT], R[NP];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int lg = wave + k * nwave;
-    V[k] = 0.f; ref[k] = 0; th[k] = 0.f; lam[k] = 0.f; rs[k] = 0.f; amp[k] = 0.f; R[k] = 0; ew[k] = 0ull;
+    V[k] = 0.f; ref[k] = 0;
+    if (!PARAMS_LDS) { th[k % NP] = 0.f; lam[k % NP] = 0.f; rs[k % NP] = 0.f; amp[k % NP] = 0.f; R[k % NP] = 0; }
     if (lg < ng) {
       const int j = (g0 + lg) * kGroup + lane;
       V[k] = n.V[static_cast<size_t>(b) * n.Npad + j];
       ref[k] = n.ref[static_cast<size_t>(b) * n.Npad + j];
-      th[k] = n.theta[j];
-      lam[k] = n.leak[j];
-      rs[k] = n.reset[j];
-      amp[k] = n.amp[j];
-      R[k] = n.refr[j];
-      if (steps > 0) ew[k] = n.ext[row_word(n, t0, b, g0 + lg)];
+      if (PARAMS_LDS) {
+        const int i = lg * kGroup + lane, s5 = a.ng_max * kGroup;
+        prm[i] = n.theta[j];
+        prm[s5 + i] = n.leak[j];
+        prm[2 * s5 + i] = n.reset[j];
+        prm[3 * s5 + i] = n.amp[j];
+        prm[4 * s5 + i] = __int_as_float(static_cast<int>(n.refr[j]));
+      } else {
+        th[k % NP] = n.theta[j];
+        lam[k % NP] = n.leak[j];
+        rs[k % NP] = n.reset[j];
+        amp[k % NP] = n.amp[j];
+        R[k % NP] = n.refr[j];
+      }
     }
   }
   __syncthreads();
 
   for (int t = t0; t < t0 + steps; ++t) {
-    uint64_t ew_next[NPT];
+    // external spike words of this step, issued first and consumed by the
+    // update (a value carried across iterations would make every wave wait
+    // for its stores at the end of the step)
+    // (the 32-bit half of the group's word that holds this lane's bit)
+    uint32_t ew[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int lg = wave + k * nwave;
-      ew_next[k] = (lg < ng && t + 1 < t0 + steps) ? n.ext[row_word(n, t + 1, b, g0 + lg)] : 0ull;
+      ew[k] = lg < ng ? reinterpret_cast<const uint32_t*>(n.ext + row_word(n, t, b, g0 + lg))[lane >> 5] : 0u;
     }
     const int cur = t % Dr;
+    float* accb = acc + (nacc == 2 ? (t & 1) * a.ng_max * kGroup : 0);
     // receive row t - 1: every word carries its step tag.  The first read of
     // this thread's word is issued before the delay >= 2 delivery, which
     // hides its latency; a word whose tag is not yet t is read again.
@@ -213,7 +431,17 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     uint64_t early = 0;
     if (receive && tid < W32) early = load_dev(mring + static_cast<size_t>(prev) * n.B * W32 + tid);
     // delay >= 2: every needed row is already held
-    deliver<RECS_LDS, RING_LDS>(n, lrec, hA, ring, mring, acc, cA0 + wave, cA1, nwave, lane, g0, r0, t, cur, Dr, W32);
+    const int cstride = mode == kModeSlot ? m : 1;
+    const int gstep = mode == kModeOwn ? nwave : 1;
+    float sum = 0.f;
+    if (mode == kModeSlot) {  // uniform per wave
+      if (team < ng)
+        sum = deliver_group<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb + team * kGroup, gsp[team],
+                                                gsp[ng + 1 + team], member, m, lane, r0, t, cur, Dr, W32);
+    } else if (wlg[0] < ng) {
+      deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb, csA, gsp, gsp + ng + 1, ng, wlg[0], wc[0], cstride,
+                                  gstep, wlo[0], whi[0], mode, lane, r0, t, cur, Dr, W32);
+    }
     if (receive) {
       const uint64_t tag = static_cast<uint64_t>(t);
       for (int i = tid; i < W32; i += nthr) {
@@ -234,16 +462,35 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     __syncthreads();
     if (MULTI && abort_flag) return false;  // uniform: read after the barrier
     // delay 1
-    deliver<RECS_LDS, RING_LDS>(n, lrec, hB, ring, mring, acc, cB0 + wave, cB1, nwave, lane, g0, r0, t, cur, Dr, W32);
-    __syncthreads();
+    if (mode == kModeSlot) {
+      if (team < ng)
+        sum += deliver_group<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb + team * kGroup, gsp[ng + 1 + team],
+                                                 gsp[team + 1], member, m, lane, r0, t, cur, Dr, W32);
+    } else if (wlg[1] < ng) {
+      deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb, csB, gsp + ng + 1, gsp + 1, ng, wlg[1], wc[1], cstride,
+                                  gstep, wlo[1], whi[1], mode, lane, r0, t, cur, Dr, W32);
+    }
+    if (mode == kModeSlot) part[wave * kGroup + lane] = sum;  // partial sums for the updating wave
+    if (mode != kModeOwn) __syncthreads();
     // fused neuron update; the ballot of a wave is the spike word of its group
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int lg = wave + k * nwave;
       if (lg < ng) {  // uniform per wave
-        const float syn = acc[lg * kGroup + lane];
-        acc[lg * kGroup + lane] = 0.f;
-        const bool s = lif_update(V[k], ref[k], syn, (ew[k] >> lane) & 1ull, th[k], lam[k], rs[k], amp[k], R[k]);
+        float syn = accb[lg * kGroup + lane];
+        accb[lg * kGroup + lane] = 0.f;
+        if (mode == kModeSlot) {
+          for (int i = 0; i < m; ++i) syn += part[(lg * m + i) * kGroup + lane];
+        }
+        bool s;
+        if (PARAMS_LDS) {
+          const int i = lg * kGroup + lane, s5 = a.ng_max * kGroup;
+          s = lif_update(V[k], ref[k], syn, (ew[k] >> (lane & 31)) & 1u, prm[i], prm[s5 + i], prm[2 * s5 + i],
+                         prm[3 * s5 + i], __float_as_int(prm[4 * s5 + i]));
+        } else {
+          s = lif_update(V[k], ref[k], syn, (ew[k] >> (lane & 31)) & 1u, th[k % NP], lam[k % NP], rs[k % NP],
+                         amp[k % NP], R[k % NP]);
+        }
         const uint64_t sw = __ballot(s);
         const int g = g0 + lg;
         if (lane == 0) n.raster[row_word(n, t, b, g)] = sw;
@@ -253,9 +500,12 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
           store_dev(mring + static_cast<size_t>(cur) * n.B * W32 + 2 * g + lane, tagged);
         }
       }
-      ew[k] = ew_next[k];
     }
-    __syncthreads();
+    // Otherwise no barrier closes the step: the next step's delay >= 2
+    // delivery reads rows up to t - 1 only, its accumulator rows are the
+    // other buffer or this wave's own, and everything that reads row t, the
+    // partial sums or the received words comes after its first barrier.
+    if (end_barrier) __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
@@ -322,8 +572,8 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, 
   if (static_cast<int>(blockIdx.x) < ba.n_team) {
     const int4 tt = ba.team[blockIdx.x];
     const SimArgs a = ba.nets[tt.x].team;
-    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true>(a, tt.y, tt.z, tt.w, steps, smem,
-                                                                             abort_flag))
+    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true, true>(a, tt.y, tt.z, tt.w, steps, smem,
+                                                                                   abort_flag))
       return;
   }
   for (;;) {
@@ -334,31 +584,44 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, 
     if (i >= ba.n_queue) return;
     const int4 qt = ba.queue[i];
     const SimArgs a = ba.nets[qt.x].single;
-    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false>(a, 0, qt.y, qt.z, steps, smem, abort_flag);
+    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false, true>(a, 0, qt.y, qt.z, steps, smem,
+                                                                               abort_flag);
   }
 }
 
-size_t batch_lds_bytes(const DevNet& n, int ng_max, int max_chunks) {
-  return static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(ng_max) * kGroup * sizeof(float) +
-         static_cast<size_t>(max_chunks) * sizeof(uint2);
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kMaxNpt = 8;
+
+// LDS of sim_body: [ring][accumulators][partial sums][group offsets][records]
+size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, bool recs_lds, bool ring_lds) {
+  size_t bytes = static_cast<size_t>(acc_rows(ng_max, nwave)) * kGroup * sizeof(float);
+  bytes += static_cast<size_t>(kMaxWaves) * kGroup * sizeof(float);
+  bytes += static_cast<size_t>(4 * ng_max + 4) * sizeof(int);
+  if (ring_lds) bytes += static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t);
+  if (recs_lds) bytes += static_cast<size_t>(max_recs) * sizeof(Rec);
+  return bytes + 64;  // static LDS of the kernel
+}
+
+size_t batch_lds_bytes(const DevNet& n, int ng_max) {
+  return sim_lds_bytes(n, ng_max, 0, kBatchThreads / 64, false, true) - 64 +
+         static_cast<size_t>(5) * ng_max * kGroup * sizeof(float);
 }
 
 int batch_blocks_per_cu(size_t lds) {
   int blocks = 0;
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(lds)) != hipSuccess)
+  const void* fn = reinterpret_cast<const void*>(&k_batch);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch, kBatchThreads, lds) != hipSuccess) return 0;
   return blocks;
 }
 
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     static_cast<int>(lds));
+  const void* fn = reinterpret_cast<const void*>(&k_batch);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
   void* args[] = {const_cast<BatchArgs*>(&a), &steps};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch), dim3(grid), dim3(kBatchThreads), args,
-                                    static_cast<unsigned>(lds), s);
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBatchThreads), args, static_cast<unsigned>(lds), s);
 }
 
 __global__ void k_zero_i32(int32_t* p) { *p = 0; }
@@ -366,18 +629,6 @@ __global__ void k_zero_i32(int32_t* p) { *p = 0; }
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, p);
   return hipGetLastError();
-}
-
-constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kMaxNpt = 8;
-
-size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int max_chunks, bool recs_lds, bool ring_lds,
-                     bool hdr_lds) {
-  size_t bytes = static_cast<size_t>(ng_max) * kGroup * sizeof(float);
-  if (hdr_lds) bytes += static_cast<size_t>(max_chunks) * sizeof(uint2);
-  if (ring_lds) bytes += static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t);
-  if (recs_lds) bytes += static_cast<size_t>(max_recs) * sizeof(Rec);
-  return bytes + 64;  // static LDS of the kernel
 }
 
 size_t lds_limit() { return kLdsLimit; }
@@ -433,7 +684,8 @@ static hipError_t launch_sim_m(const SimArgs& a, bool rl, bool gl, int32_t t0, i
 
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s) {
   if (sim_npt(a.ng_max, a.max_recs) > kMaxNpt) return hipErrorInvalidValue;
-  const size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, a.max_chunks, recs_lds, ring_lds, a.hdr_lds != 0) - 64;
+  const int nwave = sim_threads(a.ng_max, a.max_recs) / kGroup;
+  const size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, nwave, recs_lds, ring_lds) - 64;
   if (lds + 64 > kLdsLimit) return hipErrorInvalidValue;
   if (a.P > 1 || !ring_lds) {
     const hipError_t e = launch_prefill_mailbox(a, t0, s);
@@ -456,6 +708,7 @@ hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0
 template <int WAVES, int U, bool RING>
 __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
   __shared__ float acc[kGroup];
+  __shared__ float part[WAVES][kGroup];
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);  // [D][2G]: row t - d at (d - 1)
   const int g = blockIdx.x;
@@ -504,6 +757,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
     }
   }
   __syncthreads();
+  float sum = 0.f;  // lane-owned records (record k of the group is in lane k mod 64)
   for (;;) {
     uint32_t bit[U];
 #pragma unroll
@@ -522,7 +776,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (bit[u]) atomicAdd(&acc[rr[u].meta >> 26], rr[u].w);
+      const uint32_t post = rr[u].meta >> 26;
+      sum += (bit[u] && post == static_cast<uint32_t>(lane)) ? rr[u].w : 0.f;
+      if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc[post], rr[u].w);
     }
     base += WAVES * 64 * U;
     if (base >= end) break;  // uniform per wave
@@ -533,9 +789,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
       rr[u] = ok[u] ? n.recs[k] : Rec{0.f, 0u};
     }
   }
+  if (WAVES > 1) part[wave][lane] = sum;
   __syncthreads();
   if (wave == 0) {
-    const bool s = lif_update(V, ref, acc[lane], (ew >> lane) & 1ull, th, lam, rs, amp, R);
+    float syn = acc[lane] + sum;
+#pragma unroll
+    for (int i = 1; i < WAVES; ++i) syn += part[i][lane];
+    const bool s = lif_update(V, ref, syn, (ew >> lane) & 1ull, th, lam, rs, amp, R);
     const uint64_t sw = __ballot(s);
     const size_t sj = static_cast<size_t>(b) * n.Npad + j;
     n.V[sj] = V;

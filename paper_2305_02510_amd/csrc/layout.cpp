@@ -2,10 +2,19 @@
 //
 // Post-neurons are cut into groups of 64 (one wavefront, one 64-bit spike
 // word).  All synapses into a group are stored contiguously, so one workgroup
-// streams them with fully coalesced 8-byte loads.  Inside a group the records
-// are interleaved round-robin over the group's posts (first synapse of every
-// post, then the second of every post, ...), so the 64 lanes of one load
-// mostly target 64 different posts and their LDS accumulations do not collide.
+// streams them with fully coalesced 8-byte loads, in two parts: delay >= 2
+// (deliverable before the previous step's spikes are known), then delay 1.
+//
+// Inside a part the records are laid out in rows of 64 where lane l of every
+// row holds a synapse of post-neuron l ("lane-owned" rows): row r carries the
+// r-th synapse of each post, or a zero-weight filler where that post has no
+// more.  A lane then sums its post's input in a register, with no atomic
+// operation.  Rows stop at R, chosen per part to balance filler slots
+// against the synapses of the few posts with more than R; those overflow
+// records follow the rows, round-robin over their posts, padded to a
+// multiple of 64, and are accumulated with LDS atomics.  Every section is a
+// multiple of 64 records, so record k of a group sits in lane
+// (k - gptr[g]) mod 64.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -13,6 +22,33 @@
 #include "sn_internal.h"
 
 namespace snmi {
+
+namespace {
+
+// Cost model of one part: a lane-owned row costs its 64 slots, an overflow
+// record about eight slots (an LDS atomic).  Returns the best row count.
+int64_t lane_rows(const std::vector<int64_t>& deg) {
+  int64_t maxdeg = 0;
+  for (int64_t d : deg) maxdeg = std::max(maxdeg, d);
+  int64_t best_r = maxdeg, best_cost = 64 * maxdeg;
+  // overflow(R) = sum over posts of max(0, deg - R), scanned downwards
+  std::vector<int64_t> sorted(deg);
+  std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
+  int64_t over = 0;
+  size_t above = 0;  // posts with deg > R
+  for (int64_t R = maxdeg; R >= 0; --R) {
+    while (above < sorted.size() && sorted[above] > R) ++above;
+    if (R < maxdeg) over += static_cast<int64_t>(above);
+    const int64_t cost = 64 * R + 8 * ((over + 63) / 64 * 64);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best_r = R;
+    }
+  }
+  return best_r;
+}
+
+}  // namespace
 
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
                         const uint8_t* delay) {
@@ -27,57 +63,57 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
     std::vector<int64_t> fill(colptr.begin(), colptr.end() - 1);
     for (int64_t k = 0; k < nnz; ++k) order[fill[post[k]]++] = k;
   }
-  L.recs.resize(static_cast<size_t>(nnz));
+  L.recs.reserve(static_cast<size_t>(nnz) + static_cast<size_t>(nnz) / 4 + 128 * static_cast<size_t>(G));
   L.gptr.assign(static_cast<size_t>(G) + 1, 0);
   L.gsplit.assign(static_cast<size_t>(G), 0);
+  std::vector<std::vector<int64_t>> lists(kGroup);
   std::vector<int64_t> deg(kGroup);
-  std::vector<int64_t> taken(kGroup);
-  int64_t pos = 0;
   for (int32_t g = 0; g < G; ++g) {
-    L.gptr[g] = static_cast<int32_t>(pos);
+    L.gptr[g] = static_cast<int32_t>(L.recs.size());
     const int32_t j0 = g * kGroup;
     const int32_t j1 = std::min(n, j0 + kGroup);
-    // part 0: delay >= 2 (deliverable before the previous step's spikes
-    // arrive); part 1: delay 1.  Each part round-robin over the group's posts.
     for (int part = 0; part < 2; ++part) {
-      if (part == 1) L.gsplit[g] = static_cast<int32_t>(pos);
-      int64_t maxdeg = 0;
-      for (int32_t j = j0; j < j1; ++j) {
-        int64_t c = 0;
-        for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) c += ((delay[order[q]] == 1) == (part == 1));
-        deg[j - j0] = c;
-        taken[j - j0] = colptr[j];
-        maxdeg = std::max(maxdeg, c);
+      if (part == 1) L.gsplit[g] = static_cast<int32_t>(L.recs.size());
+      for (int l = 0; l < kGroup; ++l) {
+        lists[l].clear();
+        const int32_t j = j0 + l;
+        if (j < j1) {
+          for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q)
+            if ((delay[order[q]] == 1) == (part == 1)) lists[l].push_back(order[q]);
+        }
+        deg[l] = static_cast<int64_t>(lists[l].size());
       }
-      for (int64_t r = 0; r < maxdeg; ++r) {
-        for (int32_t j = j0; j < j1; ++j) {
-          if (deg[j - j0] <= r) continue;
-          int64_t q = taken[j - j0];
-          while ((delay[order[q]] == 1) != (part == 1)) ++q;  // next synapse of this part
-          taken[j - j0] = q + 1;
-          const int64_t k = order[q];
-          L.recs[pos++] = Rec{w[k], pack_meta(static_cast<uint32_t>(pre[k]), delay[k],
-                                              static_cast<uint32_t>(j - j0))};
+      // a filler names neuron 0 with a delay of this part and weight 0
+      const uint32_t fill_delay = part == 0 ? 2u : 1u;
+      const int64_t R = lane_rows(deg);
+      for (int64_t r = 0; r < R; ++r) {
+        for (int l = 0; l < kGroup; ++l) {
+          if (deg[l] > r) {
+            const int64_t k = lists[l][r];
+            L.recs.push_back(Rec{w[k], pack_meta(static_cast<uint32_t>(pre[k]), delay[k], static_cast<uint32_t>(l))});
+          } else {
+            L.recs.push_back(Rec{0.f, pack_meta(0u, fill_delay, static_cast<uint32_t>(l))});
+          }
         }
       }
-    }
-    L.max_group_records = std::max<int32_t>(L.max_group_records, static_cast<int32_t>(pos - L.gptr[g]));
-  }
-  L.gptr[G] = static_cast<int32_t>(pos);
-  // chunk table: every part-0 chunk (group order), then every part-1 chunk
-  L.gchunk.assign(2 * (static_cast<size_t>(G) + 1), 0);
-  for (int part = 0; part < 2; ++part) {
-    for (int32_t g = 0; g < G; ++g) {
-      L.gchunk[part * (G + 1) + g] = static_cast<int32_t>(L.chunks.size());
-      const int64_t b = part == 0 ? L.gptr[g] : L.gsplit[g];
-      const int64_t e = part == 0 ? L.gsplit[g] : L.gptr[g + 1];
-      for (int64_t s = b; s < e; s += kChunk) {
-        const uint32_t cnt = static_cast<uint32_t>(std::min<int64_t>(kChunk, e - s));
-        L.chunks.push_back(make_uint2(static_cast<uint32_t>(s), static_cast<uint32_t>(g) | (cnt << 20)));
+      // overflow of the posts with more than R synapses in this part
+      int64_t more = 0;
+      for (int l = 0; l < kGroup; ++l) more = std::max(more, deg[l] - R);
+      int64_t count = 0;
+      for (int64_t r = R; r < R + more; ++r) {
+        for (int l = 0; l < kGroup; ++l) {
+          if (deg[l] <= r) continue;
+          const int64_t k = lists[l][r];
+          L.recs.push_back(Rec{w[k], pack_meta(static_cast<uint32_t>(pre[k]), delay[k], static_cast<uint32_t>(l))});
+          ++count;
+        }
       }
+      for (; count % kGroup != 0; ++count)
+        L.recs.push_back(Rec{0.f, pack_meta(0u, fill_delay, static_cast<uint32_t>(count % kGroup))});
     }
-    L.gchunk[part * (G + 1) + G] = static_cast<int32_t>(L.chunks.size());
+    L.max_group_records = std::max<int32_t>(L.max_group_records, static_cast<int32_t>(L.recs.size() - L.gptr[g]));
   }
+  L.gptr[G] = static_cast<int32_t>(L.recs.size());
   return L;
 }
 
@@ -116,14 +152,7 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
   }
   greedy_slices(L, G, lo, max_groups, &p.wg_group);
   p.P = static_cast<int32_t>(p.wg_group.size()) - 1;
-  p.wg_chunk.resize(2 * p.wg_group.size());
-  for (size_t i = 0; i < p.wg_group.size(); ++i) {
-    p.wg_chunk[i] = L.gchunk[p.wg_group[i]];
-    p.wg_chunk[p.wg_group.size() + i] = L.gchunk[G + 1 + p.wg_group[i]];
-  }
-  const size_t P1 = p.wg_group.size();
   for (int32_t w = 0; w < p.P; ++w) {
-    p.max_chunks = std::max(p.max_chunks, (p.wg_chunk[w + 1] - p.wg_chunk[w]) + (p.wg_chunk[P1 + w + 1] - p.wg_chunk[P1 + w]));
     p.ng_max = std::max(p.ng_max, p.wg_group[w + 1] - p.wg_group[w]);
     p.max_recs = std::max<int64_t>(p.max_recs, L.gptr[p.wg_group[w + 1]] - L.gptr[p.wg_group[w]]);
   }

@@ -26,32 +26,29 @@ __host__ __device__ constexpr uint32_t pack_meta(uint32_t pre, uint32_t delay, u
   return pre | ((delay - 1u) << 20) | (post_local << 26);
 }
 
-// Work unit of the persistent kernel ("chunk"): up to kChunk = 4 x 64
-// consecutive records of one group, one batch of a wavefront.
-// x = first record, y = group | count << 20.
+// Work unit of a wavefront ("chunk"): kChunk = 4 x 64 consecutive records of
+// one part of one group.
 constexpr int kChunk = 256;
 
-// Host-side result of the layout builder.
+// Host-side result of the layout builder (layout.cpp): the records of every
+// group, delay >= 2 part then delay-1 part, each part in lane-owned rows of
+// 64 (lane l: a synapse of post l or a zero-weight filler) followed by the
+// overflow of high in-degree posts; every section a multiple of 64 records.
 struct HostLayout {
-  std::vector<Rec> recs;        // grouped by post-group, round-robin over posts inside a group
+  std::vector<Rec> recs;
   std::vector<int32_t> gptr;    // [G + 1] record offset of every group
   std::vector<int32_t> gsplit;  // [G] first delay-1 record of every group
-  std::vector<uint2> chunks;    // chunk table: delay >= 2 chunks of all groups, then delay-1 chunks
-  std::vector<int32_t> gchunk;  // [2][G + 1] first chunk of every group, per part
   int32_t max_group_records = 0;
 };
 
 // Partition of the groups into P contiguous slices for the persistent kernel.
 struct SlicePlan {
   std::vector<int32_t> wg_group;  // [P + 1]
-  std::vector<int32_t> wg_chunk;  // [2][P + 1]: first delay>=2 chunk, then first delay-1 chunk, per slice
   int32_t P = 0;
   int32_t ng_max = 0;
   int64_t max_recs = 0;
-  int32_t max_chunks = 0;  // most chunk headers of one slice (both parts)
   bool recs_lds = false;
   bool ring_lds = false;
-  bool hdr_lds = false;    // chunk headers copied to LDS at the start of a launch
 };
 
 // Splits groups into `slices` contiguous slices balancing record counts, no
@@ -68,8 +65,7 @@ struct DevNet {
   int32_t G;      // groups = words per spike row
   int32_t B;      // trials
   int32_t D;      // max delay
-  int32_t nchunks;
-  int64_t nnz;
+  int64_t nnz;    // synapses (records, with fillers: gptr[G])
   // per-neuron parameters, padded to Npad (padding: threshold = +inf, rest 0)
   const float* theta;
   const float* leak;
@@ -84,8 +80,8 @@ struct DevNet {
   const uint64_t* ext;
   // synapses
   const Rec* recs;
-  const int32_t* gptr;
-  const uint2* chunks;
+  const int32_t* gptr;    // [G + 1]
+  const int32_t* gsplit;  // [G] first delay-1 record of every group
 };
 
 // Arguments of the persistent kernel: the network plus a partition of its
@@ -93,14 +89,11 @@ struct DevNet {
 struct SimArgs {
   DevNet n;
   const int32_t* wg_group;  // [P + 1] first group of every slice
-  const int32_t* wg_chunk;  // [2][P + 1] first chunk of every slice: delay >= 2 part, delay-1 part
   uint64_t* mailbox;        // [D + 1][B][2G] tagged spike words: (step + 1) << 32 | 32 spike bits
   uint32_t* status;         // set to nonzero when a wait times out
   int32_t P;
   int32_t ng_max;           // most groups in one slice
   int64_t max_recs;         // most records in one slice
-  int32_t max_chunks;       // most chunk headers in one slice
-  int32_t hdr_lds;          // nonzero: chunk headers are staged in LDS
 };
 
 // Dense delay-1 weights for the matrix-core path, bfloat16, tiled for
@@ -162,7 +155,7 @@ struct BatchArgs {
 };
 
 constexpr int kBatchThreads = 512;
-constexpr int kBatchMaxGroups = 32;  // groups per slice: 8 waves x 4 groups per wave
+constexpr int kBatchMaxGroups = 24;  // groups per slice: 8 waves x 3 groups per wave
 
 }  // namespace snmi
 #include "../../include/superneuro_mi.h"
@@ -173,14 +166,13 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
                          float* dW, hipStream_t s);
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
-size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int max_chunks, bool recs_lds, bool ring_lds,
-                     bool hdr_lds);
+size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, bool recs_lds, bool ring_lds);
 size_t lds_limit();
 int sim_threads(int ng_max, int64_t max_recs);
 int sim_npt(int ng_max, int64_t max_recs);
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s);
 hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s);
-size_t batch_lds_bytes(const DevNet& n, int ng_max, int max_chunks);
+size_t batch_lds_bytes(const DevNet& n, int ng_max);
 int batch_blocks_per_cu(size_t lds);
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
