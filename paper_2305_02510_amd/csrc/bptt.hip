@@ -46,33 +46,52 @@ __device__ __forceinline__ float surrogate_grad(float x, float k) {
   return 1.f / (d * d);
 }
 
-// 32 x 32 tile of a row-major product, K staged 32 at a time.
+// 32 x 32 tile of a row-major product, K staged 128 at a time through two
+// LDS buffers (padded rows: see the kernels' declarations); the next chunk's operands are loaded into registers while the
+// matrix cores work on the current one, so there is one barrier per chunk.
 //   Aload(row, k) -> A[row][k]; Bload(k, col) -> B[k][col]
 // Returns the wave's 16 x 16 accumulator; (row0 + 16 wr + 4 (lane/16) + r,
 // col0 + 16 wc + lane % 16) is element r.
+constexpr int kTileK = 128;
+
 template <class AL, class BL>
-__device__ __forceinline__ f32x4 tile_product(int K, AL Aload, BL Bload, float (*As)[33], float (*Bs)[33]) {
+__device__ __forceinline__ f32x4 tile_product(int K, AL Aload, BL Bload, float (*As)[32][kTileK + 4],
+                                              float (*Bs)[kTileK][48]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int kc = 0; kc < K; kc += 32) {
+  // element e of this thread's share: A (row idx / kTileK, k idx % kTileK),
+  // B (k idx / 32, col idx % 32), idx = tid + 256 e
+  constexpr int kPer = 32 * kTileK / 256;
+  float ra[kPer], rb[kPer];
+  auto fetch = [&](int kc) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid + 256 * e;  // 0 .. 1023
-      const int r = idx >> 5, c = idx & 31;
-      As[r][c] = Aload(r, kc + c);
-      Bs[r][c] = Bload(kc + r, c);
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = tid + 256 * e;
+      ra[e] = Aload(idx / kTileK, kc + (idx % kTileK));
+      rb[e] = Bload(kc + (idx >> 5), idx & 31);
+    }
+  };
+  fetch(0);
+  int buf = 0;
+  for (int kc = 0; kc < K; kc += kTileK) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = tid + 256 * e;
+      As[buf][idx / kTileK][idx % kTileK] = ra[e];
+      Bs[buf][idx >> 5][idx & 31] = rb[e];
     }
     __syncthreads();
+    if (kc + kTileK < K) fetch(kc + kTileK);
 #pragma unroll
-    for (int kk = 0; kk < 32; kk += 4) {
-      const float a = As[16 * wr + (lane & 15)][kk + (lane >> 4)];
-      const float b = Bs[kk + (lane >> 4)][16 * wc + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    for (int kk = 0; kk < kTileK; kk += 4) {
+      const float av = As[buf][16 * wr + (lane & 15)][kk + (lane >> 4)];
+      const float bv = Bs[buf][kk + (lane >> 4)][16 * wc + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
     }
-    __syncthreads();
+    buf ^= 1;
   }
   return acc;
 }
@@ -86,8 +105,8 @@ __global__ __launch_bounds__(256) void k_bptt_forward(const BpttDev p, const flo
                                                       const float* __restrict__ x_t, const float* V_prev, float* s_out,
                                                       float* V_out, float* counts, float* U_keep, float* A_keep,
                                                       uint16_t* bits_out) {
-  __shared__ float As[32][33];
-  __shared__ float Bs[32][33];
+  __shared__ float As[2][32][kTileK + 4];  // row stride 132 and 48 words: the
+  __shared__ float Bs[2][kTileK][48];      // matrix-core operand reads are 2-way in the 32 banks
   const int col0 = 32 * blockIdx.x, row0 = 32 * blockIdx.y;
   const int N = p.N, Nin = p.Nin, B = p.B, K = N + Nin;
   auto Aload = [&](int r, int k) -> float {
@@ -149,8 +168,8 @@ __global__ __launch_bounds__(256) void k_bptt_backward(const BpttDev p, const fl
                                                        const float* g_next, const float* __restrict__ dcount,
                                                        const float* __restrict__ U_t, const float* __restrict__ V_t,
                                                        const float* __restrict__ s_t, float* g_out) {
-  __shared__ float As[32][33];
-  __shared__ float Bs[32][33];
+  __shared__ float As[2][32][kTileK + 4];  // row stride 132 and 48 words: the
+  __shared__ float Bs[2][kTileK][48];      // matrix-core operand reads are 2-way in the 32 banks
   const int col0 = 32 * blockIdx.x, row0 = 32 * blockIdx.y;
   const int N = p.N, B = p.B;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -184,8 +203,8 @@ __global__ __launch_bounds__(256) void k_bptt_backward(const BpttDev p, const fl
 // dW[K][N] += A^T G over M rows: A [M][K], G [M][N] (row-major).
 __global__ __launch_bounds__(256) void k_bptt_wgrad(int M, int K, int N, const float* __restrict__ A,
                                                     const float* __restrict__ G, float* dW) {
-  __shared__ float As[32][33];
-  __shared__ float Bs[32][33];
+  __shared__ float As[2][32][kTileK + 4];  // row stride 132 and 48 words: the
+  __shared__ float Bs[2][kTileK][48];      // matrix-core operand reads are 2-way in the 32 banks
   const int col0 = 32 * blockIdx.x, row0 = 32 * blockIdx.y;  // columns of dW (j), rows of dW (k)
   auto Aload = [&](int r, int m) -> float {  // (A^T)[row0 + r][m]
     const int k = row0 + r;

@@ -27,6 +27,19 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int kDenseTrials = 64;  // trials per workgroup
+
+// Eight bfloat16 {0, 1} from the bits of one byte (element e = bit e), in
+// registers: dword h holds elements 2h and 2h + 1, i.e. (b0 | b1 << 16) times
+// 0x3F80 (bfloat16 1.0).  Four VALU operations per dword, no LDS traffic.
+__device__ __forceinline__ bf16x8 expand_bits(uint32_t byte) {
+  uint32_t d[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const uint32_t b0 = (byte >> (2 * h)) & 1u, b1 = (byte >> (2 * h + 1)) & 1u;
+    d[h] = (b0 | (b1 << 16)) * 0x3F80u;
+  }
+  return __builtin_bit_cast(bf16x8, make_uint4(d[0], d[1], d[2], d[3]));
+}
 constexpr int kDenseThreads = 256;
 
 __global__ __launch_bounds__(kDenseThreads) void k_dense_step(const DenseArgs a, int t) {
@@ -151,6 +164,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_step(const DenseArgs a,
 //      exits; the other workgroups then time out the same way).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kDenseSpinLimit = 1u << 22;
+// K blocks of 128 per wave in the persistent kernel: its weight slice
+// (kpad x 16 bfloat16) must fit in LDS, so kpad <= 4480 and J / 4 <= 9.
+constexpr int kMaxJPerWave = 9;
 
 __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs a, uint32_t* flags, uint32_t* status,
                                                                  int t0, int steps) {
@@ -209,6 +225,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
   const int j0 = wave * J / 4, j1 = (wave + 1) * J / 4;
 
   for (int t = t0; t < t0 + steps; ++t) {
+    // this step's external spike bits, issued before the wait
+    uint32_t ext16[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = tb * kDenseTrials + 16 * wave + 4 * k + q;
+      ext16[k] = b < n.B ? e16[row_word(n, t, b, g) * 4 + part16] : 0u;
+    }
     if (t > t0) {
       for (int v = tid; v < ncol; v += kDenseThreads) {
         uint32_t spins = 0;
@@ -227,22 +250,32 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
 #pragma unroll
     for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (t >= 1) {
-      for (int j = j0; j < j1; ++j) {
-        uint32_t sw[4];
+      // every spike word this wave contracts, loaded at once (one memory
+      // latency per step instead of one per K block)
+      uint32_t sw[kMaxJPerWave][4];
+#pragma unroll
+      for (int jj = 0; jj < kMaxJPerWave; ++jj) {
+        const int j = j0 + jj;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           const int b = tb * kDenseTrials + 16 * m + li;
           const int wi = 4 * j + q;
-          sw[m] = (b < n.B && wi < 2 * n.G)
-                      ? __hip_atomic_load(&r32[row_word(n, t - 1, b, 0) * 2 + wi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                      : 0u;
+          sw[jj][m] = (j < j1 && b < n.B && wi < 2 * n.G)
+                          ? __hip_atomic_load(&r32[row_word(n, t - 1, b, 0) * 2 + wi], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : 0u;
         }
+      }
+#pragma unroll
+      for (int jj = 0; jj < kMaxJPerWave; ++jj) {
+        const int j = j0 + jj;
+        if (j >= j1) break;  // uniform
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const bf16x8 bfrag = __builtin_bit_cast(bf16x8, wl[(j * 4 + s) * 64 + lane]);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const bf16x8 afrag = __builtin_bit_cast(bf16x8, tab[(sw[m] >> (8 * s)) & 0xFFu]);
+            const bf16x8 afrag = expand_bits((sw[jj][m] >> (8 * s)) & 0xFFu);
             acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[m], 0, 0, 0);
           }
         }
@@ -262,7 +295,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
         float syn = 0.f;
 #pragma unroll
         for (int w = 0; w < 4; ++w) syn += part[(w * kDenseTrials + tl) * 17 + li];
-        const bool ext = (e16[row_word(n, t, b, g) * 4 + part16] >> li) & 1u;
+        const bool ext = (ext16[k] >> li) & 1u;
         s = lif_update(V[k], ref[k], syn, ext, th, lam, rs, amp, R);
       }
       const uint64_t bits = __ballot(s);
@@ -301,6 +334,7 @@ __global__ void k_dense_clear_flags(uint32_t* flags, int count) {
 hipError_t launch_dense_persist(const DenseArgs& a, uint32_t* flags, uint32_t* status, int32_t t0, int32_t steps,
                                 hipStream_t s) {
   const size_t lds = dense_persist_lds_bytes(a.kpad);
+  if (a.kpad / 128 > 4 * kMaxJPerWave) return hipErrorInvalidValue;  // the slice would not fit in LDS anyway
   const void* fn = reinterpret_cast<const void*>(&k_dense_persist);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
