@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix cores, TFLOP/s
 FP32_PEAK_TFLOPS = 157.3    # MI355X dense fp32 (matrix cores), TFLOP/s
+INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 matrix cores, TOP/s
 
 
 def events_of(raster_btn: np.ndarray, out_degree: np.ndarray) -> int:
@@ -110,13 +111,19 @@ def bench_single(args, net, kind):
            "neuron_updates_per_s": net.n * net.trials * T / (ms / 1e3)}
     sec_per_tstep = ms / 1e3 / T
     if kind == "dense":
+        # the contraction runs on int8 matrix cores when the weights allow it
+        # (integer numerators over one power of two), else on bfloat16 ones
+        i8 = path == "dense_persist_i8"
         flops = 2.0 * net.trials * net.n * net.n
         achieved = flops / sec_per_tstep / 1e12
-        w_bytes = 2.0 * net.n * net.n
+        peak = INT8_PEAK_TOPS if i8 else BF16_PEAK_TFLOPS
+        w_bytes = (1.0 if i8 else 2.0) * net.n * net.n
+        out["dtype"] = "i8 x i8 -> i32" if i8 else "bf16 x bf16 -> f32"
         out["roofline"] = {
-            "bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / BF16_PEAK_TFLOPS, 5), "traffic": None,
-            "kernel": "k_dense_persist" if path == "dense_persist" else "k_dense_step",
+            "bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TOP/s" if i8 else "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": None,
+            "kernel": {"dense_persist_i8": "k_dense_persist<true>", "dense_persist": "k_dense_persist<false>"}.get(
+                path, "k_dense_step"),
             "flops_per_time_step": flops, "us_per_time_step": round(sec_per_tstep * 1e6, 3),
             "weight_stream_GBps": round(w_bytes / sec_per_tstep / 1e9, 1),
             "weight_stream_frac_of_hbm": round(w_bytes / sec_per_tstep / 1e9 / HBM_PEAK_GBS, 4)}
@@ -353,7 +360,7 @@ def main():
         "metric": "synaptic events/sec", "value": round(r["value"], 1), "unit": "synaptic events/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 x bf16 -> f32" if args.workload == "dense_trials" else "f32",
+        "dtype": r.get("dtype", "f32"),
         "data": "synthetic (seeded Erdos-Renyi / dense nets and Bernoulli external spikes)",
         "config": cfg,
         "neuron_updates_per_s": round(r["neuron_updates_per_s"], 1),

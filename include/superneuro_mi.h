@@ -186,7 +186,10 @@ sn_status sn_set_path(sn_net* net, int32_t path);
 sn_status sn_set_slices(sn_net* net, int32_t slices);
 
 /* Reports the number of simulated steps so far (*t) and the strategy the
- * last sn_run used (*path, SN_PATH_AUTO before the first run). */
+ * last sn_run used (*path, SN_PATH_AUTO before the first run): one of the
+ * SN_PATH_* values, or 7 (a batch, sn_batch_run), 8 (SN_PATH_DENSE as one
+ * persistent launch on bfloat16 matrix cores) or 9 (the same on int8 matrix
+ * cores, used when every dense weight is k * 2^-e with |k| <= 127). */
 sn_status sn_get_progress(sn_net* net, int32_t* t, int32_t* path);
 
 /* ---- Batched execution of many independent networks --------------------

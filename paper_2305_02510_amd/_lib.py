@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "SN_OK", -1: "SN_EINVAL", -2: "SN_ENOMEM", -3: "SN_EDEVICE", 
                 -5: "SN_ERANGE", -6: "SN_EINEXACT"}
 PATH_AUTO, PATH_SMALL, PATH_STEP, PATH_PERSIST, PATH_DENSE, PATH_PUSH, PATH_DENSE_STEP = 0, 1, 2, 3, 4, 5, 6
 PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense", 5: "push", 6: "dense_step",
-              7: "batch", 8: "dense_persist"}
+              7: "batch", 8: "dense_persist", 9: "dense_persist_i8"}
 
 # Every symbol the header declares.
 EXPORTS = [

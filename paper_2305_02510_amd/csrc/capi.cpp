@@ -68,6 +68,8 @@ struct sn_net {
   int32_t push_P = 0, push_ng_max = 0;
   // dense matrix-core weights (sn_load_dense_weights)
   void* wt = nullptr;
+  void* wt8 = nullptr;   // int8 numerators when the weights allow (see DenseArgs)
+  float scale8 = 0.f;
   int32_t kpad = 0;
   bool dense_loaded = false;
   // cached graph of per-step launches
@@ -233,7 +235,7 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
     for (int32_t k = 0; k < steps; ++k) {
       hipError_t e;
       if (path == SN_PATH_DENSE) {
-        DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad};
+        DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad, nullptr, 0.f};
         e = launch_dense_step(a, t0 + k, s);
       } else {
         e = launch_step(n->d, t0 + k, s);
@@ -314,6 +316,7 @@ sn_status run_push(sn_net* n, int32_t t0, int32_t steps) {
 
 constexpr int32_t kPathBatch = 7;          // sn_get_progress after a batch run
 constexpr int32_t kPathDensePersist = 8;   // SN_PATH_DENSE ran as one cooperative launch
+constexpr int32_t kPathDensePersistI8 = 9; // ... on the int8 matrix cores
 
 bool on_device_ok(sn_net* n) {
   int cur = -1;
@@ -728,6 +731,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->synapses_loaded = true;
   dev_free(n, n->wt);
   n->wt = nullptr;
+  dev_free(n, n->wt8);
+  n->wt8 = nullptr;
   n->dense_loaded = false;
   SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
   if (!fit_plan(n->d, one)) one.P = 0;
@@ -783,6 +788,19 @@ sn_status sn_load_dense_weights(sn_net* n, const float* W, int32_t delay) {
   n->wt = wt;
   n->kpad = kpad;
   SN_HIP(n, hipMemcpyAsync(wt, tiled.data(), tiled.size() * sizeof(uint16_t), hipMemcpyHostToDevice, n->stream));
+  dev_free(n, n->wt8);
+  n->wt8 = nullptr;
+  const int32_t e8 = int8_exponent(W, static_cast<int64_t>(N) * N);
+  if (e8 >= 0) {
+    std::vector<int8_t> t8(dense_tiled_elems(n->d.Npad, kpad));
+    tile_dense_weights_i8(W, N, n->d.Npad, kpad, e8, t8.data());
+    void* w8 = dev_alloc(n, t8.size());
+    if (!w8) return fail(SN_ENOMEM, "cannot allocate dense weights");
+    SN_HIP(n, hipMemcpyAsync(w8, t8.data(), t8.size(), hipMemcpyHostToDevice, n->stream));
+    SN_HIP(n, hipStreamSynchronize(n->stream));  // t8 dies at the end of this block
+    n->wt8 = w8;
+    n->scale8 = std::ldexp(1.f, -e8);
+  }
   SN_HIP(n, hipStreamSynchronize(n->stream));
   SN_HIP(n, prepare_dense_kernel(kpad));
   n->dense_loaded = true;
@@ -897,10 +915,10 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
       if (!n->dense_loaded) return fail(SN_ESTATE, "the dense path needs sn_load_dense_weights");
       const int64_t wgs = static_cast<int64_t>(n->d.Npad / 16) * ((n->d.B + 63) / 64);
       if (path == SN_PATH_DENSE && wgs <= kMaxCoopGroups && dense_persist_lds_bytes(n->kpad) <= lds_limit()) {
-        DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad};
+        DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad, static_cast<const int8_t*>(n->wt8), n->scale8};
         SN_HIP(n, launch_dense_persist(a, n->slice_flags, n->status, n->t, n_steps, n->stream));
         n->t += n_steps;
-        n->last_path = kPathDensePersist;
+        n->last_path = n->wt8 ? kPathDensePersistI8 : kPathDensePersist;
         return SN_OK;
       }
       st = run_per_step(n, SN_PATH_DENSE, n->t, n_steps);
@@ -988,6 +1006,7 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->small.wg);
   dev_free(n, n->persist.wg);
   dev_free(n, n->wt);
+  dev_free(n, n->wt8);
   dev_free(n, n->orecs);
   dev_free(n, n->optr);
   dev_free(n, n->push_wg);

@@ -25,12 +25,23 @@ namespace snmi {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDenseTrials = 64;  // trials per workgroup
 
 // Eight bfloat16 {0, 1} from the bits of one byte (element e = bit e), in
 // registers: dword h holds elements 2h and 2h + 1, i.e. (b0 | b1 << 16) times
 // 0x3F80 (bfloat16 1.0).  Four VALU operations per dword, no LDS traffic.
+// Sixteen int8 {0, 1} from a 16-bit half of a spike word (byte i = bit i):
+// four bits spread into the four bytes of a dword by one multiply,
+// x * 0x00204081 = x + x << 7 + x << 14 + x << 21 (no carries for x < 16).
+__device__ __forceinline__ i32x4 expand_bits_i8(uint32_t half) {
+  i32x4 d;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) d[h] = static_cast<int>((((half >> (4 * h)) & 0xFu) * 0x00204081u) & 0x01010101u);
+  return d;
+}
+
 __device__ __forceinline__ bf16x8 expand_bits(uint32_t byte) {
   uint32_t d[4];
 #pragma unroll
@@ -149,27 +160,35 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_step(const DenseArgs a,
 
 // ---------------------------------------------------------------------------
 // Persistent dense kernel: all requested steps in one cooperative launch.
-// Workgroup (c, tb) keeps its 16-column slice of W in LDS for the whole run
-// (kpad x 16 bfloat16: 128 KB at N = 4096), so the weights are read from HBM
-// once per launch instead of once per step; V and the refractory counters of
-// its 64 x 16 neurons stay in registers.  Each step it
-//   1. waits until every workgroup of its trial block has published step t-1
+// Workgroup (c, tb) owns 16 post-neurons (columns 16c ..) for 64 trials.
+// Its 16-column slice of W (kpad x 16 bfloat16, 128 KB at N = 4096) is held
+// in the registers of its four waves for the whole run, each wave the
+// fragments of its quarter of K (144 registers per lane at most), so the
+// weights are read from HBM once per launch and never from LDS; V and the
+// refractory counters stay in registers.  Each step it
+//   1. issues the loads of this step's external spike bits,
+//   2. waits until every workgroup of its trial block has published step t-1
 //      (one flag per workgroup, 256 bytes apart, device-scope loads),
-//   2. loads the spike words of step t-1 it needs straight from the raster
-//      with device-scope loads (no LDS staging),
-//   3. multiplies on the matrix cores as k_dense_step does,
-//   4. updates its neurons and stores its 16 spike bits per trial with
-//      device-scope 16-bit stores, waits for them to complete, and publishes
-//      step t.  Waits are bounded (a timeout sets *status and every wave
-//      exits; the other workgroups then time out the same way).
+//   3. copies the spike bits of step t-1 of its 64 trials from the raster
+//      into LDS with coalesced device-scope 8-byte loads,
+//   4. multiplies on the matrix cores, expanding spike bits to bfloat16 in
+//      registers, and sums the four K quarters through LDS,
+//   5. applies the fused LIF update and writes 16 spike bits per trial
+//      (device-scope 16-bit stores), waits for its stores to complete, and
+//      publishes flag = t + 1.
+// Waits are bounded (a timeout sets *status and every wave exits; the other
+// workgroups then time out the same way).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kDenseSpinLimit = 1u << 22;
-// K blocks of 128 per wave in the persistent kernel: its weight slice
-// (kpad x 16 bfloat16) must fit in LDS, so kpad <= 4480 and J / 4 <= 9.
+// K blocks of 128 per wave: J / 4 <= 9, i.e. kpad <= 4608 (N <= 4608).
 constexpr int kMaxJPerWave = 9;
+// 64-bit spike words a thread stages per step: 64 trials x kpad / 64 / 256
+constexpr int kStageLoads = kDenseTrials * (4 * kMaxJPerWave * 128 / 64) / kDenseThreads;
 
-__global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs a, uint32_t* flags, uint32_t* status,
-                                                                 int t0, int steps) {
+// I8: int8 numerators on v_mfma_i32_16x16x64_i8 (see DenseArgs), else bfloat16.
+template <bool I8>
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_dense_persist(const DenseArgs a, uint32_t* flags, uint32_t* status, int t0, int steps) {
   const DevNet& n = a.n;
   const int c = blockIdx.x;
   const int tb = blockIdx.y;
@@ -180,23 +199,25 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
   const int q = lane >> 4;
   const int li = lane & 15;
   const int J = a.kpad / 128;
+  const int kw = a.kpad / 32;  // 32-bit spike words per trial row
+  const int sbw = kw + 4;      // LDS row stride: rows 4 banks apart
 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int abort_flag;
-  uint4* tab = reinterpret_cast<uint4*>(smem);                       // [256]
-  float* part = reinterpret_cast<float*>(tab + 256);                 // [4][64][17]
-  uint4* wl = reinterpret_cast<uint4*>(part + 4 * kDenseTrials * 17);  // [J][4][64] weight fragments
+  float* part = reinterpret_cast<float*>(smem);                             // [4][64][17]
+  uint32_t* sb = reinterpret_cast<uint32_t*>(part + 4 * kDenseTrials * 17);  // [64][sbw] spike words of t - 1
 
-  {
-    const uint32_t x = static_cast<uint32_t>(tid);
-    uint32_t wv[4];
+  // this wave's weight fragments: K blocks j0 .. j1 - 1, 4 steps each
+  const int j0 = wave * J / 4, j1 = (wave + 1) * J / 4;
+  constexpr int S = I8 ? 2 : 4;  // matrix-core steps per K block of 128
+  const uint4* wsrc = I8 ? reinterpret_cast<const uint4*>(a.wt8) + static_cast<size_t>(c) * J * 2 * 64
+                         : reinterpret_cast<const uint4*>(a.wt) + static_cast<size_t>(c) * J * 4 * 64;
+  uint4 wreg[kMaxJPerWave][S];
 #pragma unroll
-    for (int h = 0; h < 4; ++h)
-      wv[h] = (((x >> (2 * h)) & 1u) ? 0x3F80u : 0u) | (((x >> (2 * h + 1)) & 1u) ? 0x3F800000u : 0u);
-    tab[tid] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-  }
-  const uint4* wsrc = reinterpret_cast<const uint4*>(a.wt) + static_cast<size_t>(c) * J * 4 * 64;
-  for (int i = tid; i < J * 4 * 64; i += kDenseThreads) wl[i] = wsrc[i];
+  for (int jj = 0; jj < kMaxJPerWave; ++jj)
+#pragma unroll
+    for (int s = 0; s < S; ++s) wreg[jj][s] = j0 + jj < j1 ? wsrc[((j0 + jj) * S + s) * 64 + lane] : make_uint4(0, 0, 0, 0);
+  const float scale = I8 ? a.scale8 : 1.f;
   if (tid == 0) abort_flag = 0;
 
   // neuron state: lane (q, li) of wave w, pass k -> trial 16w + 4k + q, column li
@@ -217,12 +238,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
   }
   __syncthreads();
 
-  const uint32_t* r32 = reinterpret_cast<const uint32_t*>(n.raster);
   const uint16_t* e16 = reinterpret_cast<const uint16_t*>(n.ext);
   uint16_t* o16 = reinterpret_cast<uint16_t*>(n.raster);
   uint32_t* myflags = flags + static_cast<size_t>(tb) * ncol * 64;
   const int g = c >> 2, part16 = c & 3;
-  const int j0 = wave * J / 4, j1 = (wave + 1) * J / 4;
 
   for (int t = t0; t < t0 + steps; ++t) {
     // this step's external spike bits, issued before the wait
@@ -247,45 +266,79 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
       if (abort_flag) return;  // uniform: read after the barrier
     }
     f32x4 acc[4];
+    i32x4 acc8[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 4; ++m) {
+      acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc8[m] = i32x4{0, 0, 0, 0};
+    }
     if (t >= 1) {
-      // every spike word this wave contracts, loaded at once (one memory
-      // latency per step instead of one per K block)
-      uint32_t sw[kMaxJPerWave][4];
+      // spike words of step t - 1 of the 64 trials, 64-bit words coalesced;
+      // all of a thread's loads are issued before the first LDS store
+      const int nw64 = kw / 2;
+      uint64_t v[kStageLoads];
 #pragma unroll
-      for (int jj = 0; jj < kMaxJPerWave; ++jj) {
-        const int j = j0 + jj;
+      for (int e = 0; e < kStageLoads; ++e) {
+        const int i = tid + kDenseThreads * e;
+        const int tr = i / nw64, w = i - tr * nw64;
+        const int b = tb * kDenseTrials + tr;
+        v[e] = 0;
+        if (i < kDenseTrials * nw64 && b < n.B && w < n.G)
+          v[e] = __hip_atomic_load(&n.raster[row_word(n, t - 1, b, w)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int b = tb * kDenseTrials + 16 * m + li;
-          const int wi = 4 * j + q;
-          sw[jj][m] = (j < j1 && b < n.B && wi < 2 * n.G)
-                          ? __hip_atomic_load(&r32[row_word(n, t - 1, b, 0) * 2 + wi], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)
-                          : 0u;
+      for (int e = 0; e < kStageLoads; ++e) {
+        const int i = tid + kDenseThreads * e;
+        const int tr = i / nw64, w = i - tr * nw64;
+        if (i < kDenseTrials * nw64) {
+          sb[tr * sbw + 2 * w] = static_cast<uint32_t>(v[e]);
+          sb[tr * sbw + 2 * w + 1] = static_cast<uint32_t>(v[e] >> 32);
         }
       }
+      __syncthreads();
 #pragma unroll
       for (int jj = 0; jj < kMaxJPerWave; ++jj) {
         const int j = j0 + jj;
         if (j >= j1) break;  // uniform
+        uint32_t sw[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const bf16x8 bfrag = __builtin_bit_cast(bf16x8, wl[(j * 4 + s) * 64 + lane]);
+        for (int m = 0; m < 4; ++m) sw[m] = sb[(16 * m + li) * sbw + 4 * j + q];
+        if constexpr (I8) {
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const bf16x8 afrag = expand_bits((sw[jj][m] >> (8 * s)) & 0xFFu);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[m], 0, 0, 0);
+          for (int s = 0; s < 2; ++s) {
+            const i32x4 bfrag = __builtin_bit_cast(i32x4, wreg[jj][s]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+              acc8[m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(expand_bits_i8((sw[m] >> (16 * s)) & 0xFFFFu), bfrag,
+                                                              acc8[m], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const bf16x8 bfrag = __builtin_bit_cast(bf16x8, wreg[jj][s]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+              acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(expand_bits((sw[m] >> (8 * s)) & 0xFFu), bfrag, acc[m],
+                                                               0, 0, 0);
           }
         }
       }
     }
+    // partial sums (int8 path: integers below 2^24, exact as floats)
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) part[(wave * kDenseTrials + 16 * m + 4 * q + r) * 17 + li] = acc[m][r];
+      for (int r = 0; r < 4; ++r)
+        part[(wave * kDenseTrials + 16 * m + 4 * q + r) * 17 + li] = I8 ? static_cast<float>(acc8[m][r]) : acc[m][r];
     __syncthreads();
+    // the external bits, taken before this step's first store (a load
+    // consumed after a store would wait for that store to complete)
+    uint32_t em = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) em |= ((ext16[k] >> li) & 1u) << k;
+    // all four updates first, then one store for the four words (a store
+    // between updates would make the next one wait for it)
+    uint32_t word16[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int tl = 16 * wave + 4 * k + q;
@@ -295,13 +348,18 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
         float syn = 0.f;
 #pragma unroll
         for (int w = 0; w < 4; ++w) syn += part[(w * kDenseTrials + tl) * 17 + li];
-        const bool ext = (ext16[k] >> li) & 1u;
+        syn *= scale;  // a power of two: exact
+        const bool ext = (em >> k) & 1u;
         s = lif_update(V[k], ref[k], syn, ext, th, lam, rs, amp, R);
       }
-      const uint64_t bits = __ballot(s);
-      if (li == 0 && b < n.B)
-        __hip_atomic_store(&o16[row_word(n, t, b, g) * 4 + part16], static_cast<uint16_t>(bits >> (16 * q)),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      word16[k] = static_cast<uint32_t>(__ballot(s) >> (16 * q)) & 0xFFFFu;
+    }
+    {  // one store instruction: lane (q, k) writes the word of trial 16 w + 4 k + q
+      const uint32_t mine = li == 0 ? word16[0] : li == 1 ? word16[1] : li == 2 ? word16[2] : word16[3];
+      const int b = tb * kDenseTrials + 16 * wave + 4 * li + q;
+      if (li < 4 && b < n.B)
+        __hip_atomic_store(&o16[row_word(n, t, b, g) * 4 + part16], static_cast<uint16_t>(mine), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
     // publish step t once this workgroup's spike words are complete
     __builtin_amdgcn_s_waitcnt(0);
@@ -320,7 +378,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_persist(const DenseArgs
 }
 
 size_t dense_persist_lds_bytes(int32_t kpad) {
-  return 256 * sizeof(uint4) + 4 * kDenseTrials * 17 * sizeof(float) + static_cast<size_t>(kpad) * 16 * sizeof(uint16_t);
+  if (kpad / 128 > 4 * kMaxJPerWave) return static_cast<size_t>(1) << 30;  // weights do not fit in registers
+  return 4 * kDenseTrials * 17 * sizeof(float) + static_cast<size_t>(kDenseTrials) * (kpad / 32 + 4) * sizeof(uint32_t);
 }
 
 __global__ void k_dense_clear_flags(uint32_t* flags, int count) {
@@ -334,8 +393,9 @@ __global__ void k_dense_clear_flags(uint32_t* flags, int count) {
 hipError_t launch_dense_persist(const DenseArgs& a, uint32_t* flags, uint32_t* status, int32_t t0, int32_t steps,
                                 hipStream_t s) {
   const size_t lds = dense_persist_lds_bytes(a.kpad);
-  if (a.kpad / 128 > 4 * kMaxJPerWave) return hipErrorInvalidValue;  // the slice would not fit in LDS anyway
-  const void* fn = reinterpret_cast<const void*>(&k_dense_persist);
+  if (a.kpad / 128 > 4 * kMaxJPerWave) return hipErrorInvalidValue;  // weights would not fit in registers
+  const void* fn = a.wt8 ? reinterpret_cast<const void*>(&k_dense_persist<true>)
+                         : reinterpret_cast<const void*>(&k_dense_persist<false>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
   const dim3 grid(a.n.Npad / 16, (a.n.B + kDenseTrials - 1) / kDenseTrials);

@@ -16,6 +16,7 @@
 // multiple of 64 records, so record k of a group sits in lane
 // (k - gptr[g]) mod 64.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 
@@ -194,6 +195,35 @@ void tile_dense_weights(const float* W, int32_t n, int32_t npad, int32_t kpad, u
               const int32_t k = 8 * (16 * j + 4 * q + s) + e;
               const int32_t jj = 16 * c + col;
               out[o++] = (k < n && jj < n) ? bf16_bits(W[static_cast<size_t>(k) * n + jj]) : uint16_t(0);
+            }
+}
+
+int32_t int8_exponent(const float* W, int64_t count) {
+  for (int32_t e = 0; e <= 24; ++e) {
+    const float f = std::ldexp(1.f, e);
+    bool ok = true;
+    for (int64_t i = 0; i < count && ok; ++i) {
+      const float v = W[i] * f;  // exact: scaling by a power of two
+      ok = std::fabs(v) <= 127.f && v == std::nearbyint(v);
+    }
+    if (ok) return e;
+  }
+  return -1;
+}
+
+void tile_dense_weights_i8(const float* W, int32_t n, int32_t npad, int32_t kpad, int32_t e, int8_t* out) {
+  const int32_t C = npad / 16, J = kpad / 128;
+  const float f = std::ldexp(1.f, e);
+  size_t o = 0;
+  for (int32_t c = 0; c < C; ++c)
+    for (int32_t j = 0; j < J; ++j)
+      for (int32_t s = 0; s < 2; ++s)
+        for (int32_t q = 0; q < 4; ++q)
+          for (int32_t col = 0; col < 16; ++col)
+            for (int32_t i = 0; i < 16; ++i) {
+              const int32_t k = 32 * (4 * j + q) + 16 * s + i;
+              const int32_t jj = 16 * c + col;
+              out[o++] = (k < n && jj < n) ? static_cast<int8_t>(W[static_cast<size_t>(k) * n + jj] * f) : int8_t(0);
             }
 }
 

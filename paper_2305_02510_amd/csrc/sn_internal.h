@@ -102,14 +102,27 @@ struct SimArgs {
 // at step (j, s) lane group q contracts pre-neurons 8 * (16 j + 4 q + s) + e,
 // e = 0..7, so one 32-bit word of a trial's spike bits feeds four steps.
 // Element (col tile c, j, s, q, col, e) = W[8 (16 j + 4 q + s) + e][16 c + col].
+//
+// When every weight is an integer multiple k * 2^-e of one power of two with
+// |k| <= 127, the weights are also kept as int8 numerators for
+// v_mfma_i32_16x16x64_i8: the same K blocks j of 128 in 2 steps s x 4 lane
+// groups q x 16, lane group q at step (j, s) contracting pre-neurons
+// 32 (4 j + q) + 16 s + i, i = 0..15 (one 16-bit half of a spike word).
+// Element (col tile c, j, s, q, col, i) = k(W[32 (4j+q) + 16 s + i][16 c + col]).
+// Integer products and sums are exact; the sum times 2^-e is the exact input.
 struct DenseArgs {
   DevNet n;
   const uint16_t* wt;  // [Npad / 16][kpad / 128][4][4][16][8] bf16 bits
   int32_t kpad;
+  const int8_t* wt8;   // [Npad / 16][kpad / 128][2][4][16][16] int8 numerators, or null
+  float scale8;        // 2^-e
 };
 
 size_t dense_tiled_elems(int32_t npad, int32_t kpad);
 void tile_dense_weights(const float* W, int32_t n, int32_t npad, int32_t kpad, uint16_t* out);
+// Smallest e in [0, 24] with every W * 2^e an integer of magnitude <= 127, or -1.
+int32_t int8_exponent(const float* W, int64_t count);
+void tile_dense_weights_i8(const float* W, int32_t n, int32_t npad, int32_t kpad, int32_t e, int8_t* out);
 
 // Event-driven ("push") delivery: out-going synapses of every neuron (CSR by
 // pre-neuron) and a ring of D + 1 accumulator rows; a spike of neuron i at t

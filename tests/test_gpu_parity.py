@@ -4,6 +4,7 @@ Inputs are dyadic, so every sum is exact in binary32 and the oracle's double
 results are the unique answer: rasters must match exactly, membrane states at
 0 ULP and refractory counters exactly.
 """
+import dataclasses
 import os
 import sys
 
@@ -218,15 +219,31 @@ def test_error_paths(gpu):
     g.close()
 
 
+def bf16_only(net):
+    """The same dense net with one weight (W[0][1] = 3) that no common
+    power-of-two scale brings to int8 next to the k/64 weights, so the dense
+    path must take the bfloat16 matrix cores."""
+    W = net.dense_weight.copy()
+    W[0, 1] = 3.0
+    return dataclasses.replace(net, dense_weight=W)
+
+
 def test_dense_trials_small(gpu, oracle):
-    """Dense weights on the matrix cores: several trials, ragged N and B."""
+    """Dense weights on the matrix cores: several trials, ragged N and B, on
+    the int8 path (weights k/64, |k| <= 16) and the bfloat16 path."""
     for (n, trials, seed) in [(100, 3, 31), (256, 17, 32), (130, 64, 33), (64, 70, 34)]:
-        net = wl.dense_trials(seed, n=n, trials=trials, steps=60, drive_p=0.05)
-        res = oracle.run_dense(net)
-        for path in ("dense", "dense_step", "step", "persist", "push"):
-            s, V, r, used = simulate(gpu, net, path, chunks=[25, 35])
-            assert used == {"dense": "dense_persist"}.get(path, path) or (path == "dense" and used == "dense")
-            assert_parity(net, res, s, V, r, f"{path} n={n} trials={trials}")
+        for variant in ("i8", "bf16"):
+            net = wl.dense_trials(seed, n=n, trials=trials, steps=60, drive_p=0.05)
+            if variant == "bf16":
+                net = bf16_only(net)
+            res = oracle.run_dense(net)
+            persist = "dense_persist_i8" if variant == "i8" else "dense_persist"
+            for path in ("dense", "dense_step", "step", "persist", "push"):
+                if variant == "bf16" and path in ("step", "persist", "push"):
+                    continue
+                s, V, r, used = simulate(gpu, net, path, chunks=[25, 35])
+                assert used == {"dense": persist}.get(path, path), (path, used)
+                assert_parity(net, res, s, V, r, f"{path} {variant} n={n} trials={trials}")
 
 
 def test_dense_trials_full_sampled(gpu, oracle):
@@ -235,7 +252,7 @@ def test_dense_trials_full_sampled(gpu, oracle):
     net = wl.dense_trials(3)
     g = gpu.from_workload(net)
     g.run(net.steps)
-    assert g.progress[1] == "dense_persist"
+    assert g.progress[1] == "dense_persist_i8"
     spikes = g.read_raster(0, net.steps)
     V, ref = g.read_state()
     g.close()
@@ -249,6 +266,23 @@ def test_dense_trials_full_sampled(gpu, oracle):
     from oracle_pins import check_refractory
     check_refractory(spikes[:, :300], net.refractory)
     assert 0.001 < spikes.mean() < 0.2
+
+
+def test_dense_full_bf16_sampled(gpu, oracle):
+    """The benchmarked dense workload on the bfloat16 matrix cores (one weight
+    changed so that int8 does not apply), 400 steps, one trial checked."""
+    net = bf16_only(wl.dense_trials(3))
+    g = gpu.from_workload(net)
+    g.run(400)
+    assert g.progress[1] == "dense_persist"
+    spikes = g.read_raster(0, 400)
+    V, ref = g.read_state()
+    g.close()
+    res = oracle.run_dense(net, steps=400, trials=[5])
+    assert res.exact
+    assert np.array_equal(spikes[[5]], res.spikes)
+    assert np.array_equal(V[[5]].astype(np.float64), res.V)
+    assert np.array_equal(ref[[5]].astype(np.int32), res.ref)
 
 
 def test_batch_uneven(gpu, oracle):
