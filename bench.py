@@ -94,7 +94,11 @@ def bench_single(args, net, kind):
     from paper_2305_02510_amd import Network
     T = net.steps
     g = Network.from_workload(net)
-    g.set_path(args.path)
+    tuned = None
+    if args.path == "autotune":  # the library's autotuner picks path and slice count
+        tuned = g.autotune(min(T, 128))
+    else:
+        g.set_path(args.path)
 
     def one_run():
         g.reset_state()
@@ -107,7 +111,7 @@ def bench_single(args, net, kind):
     g.close()
     ev = events_of(raster, net.out_degree())
     out = {"value": ev / (ms / 1e3), "ms_per_step": ms, "wall": wall, "events_per_run": ev,
-           "mean_firing_rate": float(raster.mean()), "path": path,
+           "mean_firing_rate": float(raster.mean()), "path": path, "autotuned": tuned,
            "neuron_updates_per_s": net.n * net.trials * T / (ms / 1e3)}
     sec_per_tstep = ms / 1e3 / T
     if kind == "dense":
@@ -305,7 +309,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_sparse",
                     choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch", "bptt"])
-    ap.add_argument("--path", default="auto")
+    ap.add_argument("--path", default="autotune",
+                    help="autotune (sn_autotune picks), auto (built-in heuristic) or a path name")
     ap.add_argument("--cpu-trials", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -356,6 +361,8 @@ def main():
         cfg = {"workload": f"{net.name}: N={net.n}, nnz={net.nnz}, D={net.max_delay}, T={net.steps}, "
                            f"trials={net.trials}", "time_steps_per_run": net.steps, "trials": net.trials}
     cfg["path"] = r["path"]
+    if r.get("autotuned"):
+        cfg["autotuned"] = {"path": r["autotuned"][0], "slices": r["autotuned"][1]}
     out = {
         "metric": "synaptic events/sec", "value": round(r["value"], 1), "unit": "synaptic events/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),

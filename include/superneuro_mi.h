@@ -185,6 +185,20 @@ sn_status sn_set_path(sn_net* net, int32_t path);
  * Errors: SN_ERANGE. */
 sn_status sn_set_slices(sn_net* net, int32_t slices);
 
+/* Autotuner: times every strategy that can run this network (the
+ * single-workgroup and multi-slice persistent kernels, the latter at several
+ * slice counts, the per-step and event-driven paths; for dense weights the
+ * persistent and per-step matrix-core paths) over `steps` steps from the
+ * initial state, each after one untimed run of the same length, with HIP
+ * events on the network's stream.  The fastest becomes the network's path and
+ * slice count, as if set with sn_set_path / sn_set_slices; results do not
+ * depend on the choice.  Uses the external spikes already set for those
+ * steps.  The state is reset (t = 0) before every trial and at the end.
+ * *path_out / *slices_out (either may be NULL) receive the choice
+ * (slices 0 = the default plan).  1 <= steps <= 4096, else SN_ERANGE; a
+ * device error poisons the network as sn_run would. */
+sn_status sn_autotune(sn_net* net, int32_t steps, int32_t* path_out, int32_t* slices_out);
+
 /* Reports the number of simulated steps so far (*t) and the strategy the
  * last sn_run used (*path, SN_PATH_AUTO before the first run): one of the
  * SN_PATH_* values, or 7 (a batch, sn_batch_run), 8 (SN_PATH_DENSE as one

@@ -18,7 +18,8 @@ PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense", 5: "pu
 EXPORTS = [
     "sn_create_network", "sn_load_weights_delays", "sn_load_dense_weights", "sn_set_input_spikes",
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
-    "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_get_progress", "sn_destroy_network", "sn_last_error",
+    "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_autotune", "sn_get_progress", "sn_destroy_network",
+    "sn_last_error",
     "sn_batch_create", "sn_batch_run", "sn_batch_destroy",
     "sn_bptt_workspace_bytes", "sn_bptt_forward", "sn_bptt_backward",
 ]
@@ -74,6 +75,7 @@ def load():
         "sn_reset_state": [P],
         "sn_set_path": [P, I32],
         "sn_set_slices": [P, I32],
+        "sn_autotune": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "sn_get_progress": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "sn_batch_create": [P, I32, ctypes.POINTER(P)],
         "sn_batch_run": [P, I32],

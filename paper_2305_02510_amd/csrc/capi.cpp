@@ -986,6 +986,84 @@ sn_status sn_read_state(sn_net* n, float* V, uint8_t* refractory_left) {
   return SN_OK;
 }
 
+sn_status sn_autotune(sn_net* n, int32_t steps, int32_t* path_out, int32_t* slices_out) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_autotune");
+  if (steps < 1 || steps > 4096) return fail(SN_ERANGE, "steps %d outside [1, 4096]", steps);
+  if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
+  struct Cand {
+    int32_t path, slices;
+  };
+  std::vector<Cand> cands;
+  if (n->dense_loaded) {
+    cands = {{SN_PATH_DENSE, 0}, {SN_PATH_DENSE_STEP, 0}};
+  } else {
+    if (n->small.ok) cands.push_back({SN_PATH_SMALL, 0});
+    const int32_t top = std::min(n->d.G, std::max(1, kMaxCoopGroups / n->d.B));
+    const int32_t least = std::max(2, (n->d.G + 127) / 128);
+    int32_t last = -1;
+    for (int32_t div : {1, 2, 4, 8}) {
+      const int32_t s = top / div;
+      if (s < least || s == last) continue;
+      last = s;
+      SlicePlan p = plan_persist(n->d, n->layout, s);
+      if (p.P > 1) cands.push_back({SN_PATH_PERSIST, div == 1 ? 0 : s});
+    }
+    cands.push_back({SN_PATH_STEP, 0});
+    cands.push_back({SN_PATH_PUSH, 0});
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SN_HIP(n, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return device_error(n, hipErrorOutOfMemory, "hipEventCreate");
+  }
+  Cand best{SN_PATH_AUTO, 0};
+  float best_ms = 0.f;
+  for (const Cand& c : cands) {
+    n->path = c.path;
+    if (c.path == SN_PATH_PERSIST || n->slices_req != c.slices) {
+      n->slices_req = c.slices;
+      st = upload_plan(n, n->persist, plan_persist(n->d, n->layout, c.slices));
+      if (st != SN_OK) break;
+    }
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && st == SN_OK; ++rep) {  // untimed run, then the timed one
+      st = sn_reset_state(n);
+      if (st == SN_OK && hipEventRecord(e0, n->stream) != hipSuccess) st = device_error(n, hipErrorUnknown, "hipEventRecord");
+      if (st == SN_OK) st = sn_run(n, steps);
+      if (st == SN_OK && hipEventRecord(e1, n->stream) != hipSuccess) st = device_error(n, hipErrorUnknown, "hipEventRecord");
+      if (st == SN_OK) st = sn_synchronize(n);
+      if (st == SN_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = device_error(n, hipErrorUnknown, "hipEventElapsedTime");
+    }
+    if (st != SN_OK) {
+      if (n->poisoned) break;
+      st = SN_OK;  // this strategy cannot run the network (e.g. a size limit): skip it
+      continue;
+    }
+    if (best.path == SN_PATH_AUTO || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SN_OK) return st;
+  if (best.path == SN_PATH_AUTO) return fail(SN_ERANGE, "no strategy could run the network");
+  n->path = best.path;
+  if (n->slices_req != best.slices) {
+    n->slices_req = best.slices;
+    st = upload_plan(n, n->persist, plan_persist(n->d, n->layout, best.slices));
+    if (st != SN_OK) return st;
+  }
+  st = sn_reset_state(n);
+  if (st != SN_OK) return st;
+  if (path_out) *path_out = best.path;
+  if (slices_out) *slices_out = best.slices;
+  return SN_OK;
+}
+
 sn_status sn_reset_state(sn_net* n) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;

@@ -140,6 +140,14 @@ class Network:
     def set_slices(self, slices: int):
         check(self.lib.sn_set_slices(self.h, int(slices)))
 
+    def autotune(self, steps: int = 64):
+        """Times every strategy that can run this network over `steps` steps
+        (sn_autotune) and keeps the fastest; resets the state.  Returns the
+        chosen (path name, slice count; 0 = default plan)."""
+        path, slices = ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.sn_autotune(self.h, int(steps), ctypes.byref(path), ctypes.byref(slices)))
+        return _lib.PATH_NAMES.get(path.value, str(path.value)), slices.value
+
     def run(self, steps: int):
         check(self.lib.sn_run(self.h, int(steps)))
 

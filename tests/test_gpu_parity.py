@@ -285,6 +285,35 @@ def test_dense_full_bf16_sampled(gpu, oracle):
     assert np.array_equal(ref[[5]].astype(np.int32), res.ref)
 
 
+def test_autotune_sparse_and_dense(gpu, oracle):
+    """The autotuner's choice runs bit-exact, is reported by the next run, and
+    leaves the state reset; for sparse and dense weights."""
+    net = wl.random_small(77, n=1500, p=0.03, max_delay=6, steps=150, trials=2)
+    res = oracle.run_sparse(net)
+    g = gpu.from_workload(net)
+    path, slices = g.autotune(64)
+    assert path in ("small", "persist", "step", "push") and slices >= 0
+    assert g.progress[0] == 0
+    g.run(70)
+    g.run(80)
+    assert g.progress[1] == path
+    spikes = g.read_raster(0, net.steps)
+    V, ref = g.read_state()
+    g.close()
+    assert_parity(net, res, spikes, V, ref, f"autotuned {path}/{slices}")
+
+    dnet = wl.dense_trials(35, n=200, trials=9, steps=60, drive_p=0.05)
+    dres = oracle.run_dense(dnet)
+    g = gpu.from_workload(dnet)
+    path, _ = g.autotune(30)
+    assert path in ("dense", "dense_step")
+    g.run(dnet.steps)
+    spikes = g.read_raster(0, dnet.steps)
+    V, ref = g.read_state()
+    g.close()
+    assert_parity(dnet, dres, spikes, V, ref, f"autotuned dense {path}")
+
+
 def test_batch_uneven(gpu, oracle):
     """Uneven batch of independent nets in one persistent launch: every net
     bit-exact against its own oracle run, resumed over two batch runs."""
