@@ -137,7 +137,8 @@ def bench_single(args, net, kind):
         kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)", "step": "k_step",
                   "push": "k_push"}.get(path, path)
         traffic = None
-        if path == "persist" and net.name.startswith("large_sparse_n10000"):
+        if path == "persist" and net.name.startswith("large_sparse_n10000") and (tuned is None or tuned[1] == 0):
+            # counters taken on the default slice plan
             traffic = measured_traffic("large_sparse_k_sim_persist_hbm_traffic.txt", "kernels.hip")
         out["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
