@@ -14,10 +14,12 @@
 //   dW_cat = sum_t [s_{t-1} | x_t]^T g_t
 //
 // All three products use one tile scheme: a workgroup of 4 waves computes a
-// 32 x 32 output tile, K in chunks of 32 staged through LDS, each wave one
-// 16 x 16 accumulator.  Operand layout of v_mfma_f32_16x16x4_f32: lane l
-// holds A[l % 16][l / 16] and B[l / 16][l % 16]; the result D[4 (l/16) + r]
-// [l % 16], r = 0..3.
+// 64 x 64 output tile, K in chunks of 64 staged through two LDS buffers, each
+// wave 2 x 2 accumulators of 16 x 16.  The per-step products (128 trials:
+// few output tiles) split K over several workgroups and a small epilogue
+// kernel sums the parts in a fixed order and applies the step.  Operand
+// layout of v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; the result D[4 (l/16) + r][l % 16], r = 0..3.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,166 +48,189 @@ __device__ __forceinline__ float surrogate_grad(float x, float k) {
   return 1.f / (d * d);
 }
 
-// 32 x 32 tile of a row-major product, K staged 128 at a time through two
-// LDS buffers (padded rows: see the kernels' declarations); the next chunk's operands are loaded into registers while the
-// matrix cores work on the current one, so there is one barrier per chunk.
-//   Aload(row, k) -> A[row][k]; Bload(k, col) -> B[k][col]
-// Returns the wave's 16 x 16 accumulator; (row0 + 16 wr + 4 (lane/16) + r,
-// col0 + 16 wc + lane % 16) is element r.
-constexpr int kTileK = 128;
+// 64 x 64 tile of a row-major product, K staged 64 at a time through two
+// LDS buffers with the next chunk prefetched into registers.  Wave (wr, wc)
+// owns the 32 x 32 quarter (32 wr .., 32 wc ..) as 2 x 2 accumulators of
+// 16 x 16, so every pair of operand reads feeds two matrix-core operations.
+// acc[rb][cb] element r is (row0 + 32 wr + 16 rb + 4 (lane/16) + r,
+// col0 + 32 wc + 16 cb + lane % 16).
+constexpr int kT64 = 64;
+struct Acc64 {
+  f32x4 v[2][2];
+};
 
 template <class AL, class BL>
-__device__ __forceinline__ f32x4 tile_product(int K, AL Aload, BL Bload, float (*As)[32][kTileK + 4],
-                                              float (*Bs)[kTileK][48]) {
+__device__ __forceinline__ Acc64 tile_product64(int k0, int K, AL Aload, BL Bload, float (*As)[64][kT64 + 4],
+                                                float (*Bs)[kT64][80]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  // element e of this thread's share: A (row idx / kTileK, k idx % kTileK),
-  // B (k idx / 32, col idx % 32), idx = tid + 256 e
-  constexpr int kPer = 32 * kTileK / 256;
+  Acc64 acc;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc.v[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // element e of this thread's share: A (row idx / 64, k idx % 64), B (k idx / 64, col idx % 64)
+  constexpr int kPer = 64 * kT64 / 256;
   float ra[kPer], rb[kPer];
   auto fetch = [&](int kc) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int idx = tid + 256 * e;
-      ra[e] = Aload(idx / kTileK, kc + (idx % kTileK));
-      rb[e] = Bload(kc + (idx >> 5), idx & 31);
+      ra[e] = Aload(idx >> 6, kc + (idx & 63));
+      rb[e] = Bload(kc + (idx >> 6), idx & 63);
     }
   };
-  fetch(0);
+  fetch(k0);
   int buf = 0;
-  for (int kc = 0; kc < K; kc += kTileK) {
+  for (int kc = k0; kc < K; kc += kT64) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int idx = tid + 256 * e;
-      As[buf][idx / kTileK][idx % kTileK] = ra[e];
-      Bs[buf][idx >> 5][idx & 31] = rb[e];
+      As[buf][idx >> 6][idx & 63] = ra[e];
+      Bs[buf][idx >> 6][idx & 63] = rb[e];
     }
     __syncthreads();
-    if (kc + kTileK < K) fetch(kc + kTileK);
+    if (kc + kT64 < K) fetch(kc + kT64);
 #pragma unroll
-    for (int kk = 0; kk < kTileK; kk += 4) {
-      const float av = As[buf][16 * wr + (lane & 15)][kk + (lane >> 4)];
-      const float bv = Bs[buf][kk + (lane >> 4)][16 * wc + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    for (int kk = 0; kk < kT64; kk += 4) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = As[buf][32 * wr + 16 * i + (lane & 15)][kk + (lane >> 4)];
+        bv[i] = Bs[buf][kk + (lane >> 4)][32 * wc + 16 * i + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc.v[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc.v[i][j], 0, 0, 0);
     }
     buf ^= 1;
   }
   return acc;
 }
 
-// Forward step t: tile (cols 32 blockIdx.x .., trials 32 blockIdx.y ..).
-// s_prev [B][N] (null: no spikes yet), V_prev [B][N] (null: rest state),
-// x_t [B][Nin].  Writes s_out, V_out [B][N]; adds s into counts; optionally
-// keeps U [B][N], the A row [B][N + Nin], and bit-packed spikes [B][N/32]
-// (16-bit halves per wave, N a multiple of 32).
-__global__ __launch_bounds__(256) void k_bptt_forward(const BpttDev p, const float* __restrict__ W, const float* s_prev,
-                                                      const float* __restrict__ x_t, const float* V_prev, float* s_out,
-                                                      float* V_out, float* counts, float* U_keep, float* A_keep,
-                                                      uint16_t* bits_out) {
-  __shared__ float As[2][32][kTileK + 4];  // row stride 132 and 48 words: the
-  __shared__ float Bs[2][kTileK][48];      // matrix-core operand reads are 2-way in the 32 banks
-  const int col0 = 32 * blockIdx.x, row0 = 32 * blockIdx.y;
-  const int N = p.N, Nin = p.Nin, B = p.B, K = N + Nin;
+// Per-step products, K split over gridDim.z workgroups (each a multiple of
+// kT64): tile (cols 64 blockIdx.x .., trials 64 blockIdx.y ..) of part z
+// of   forward:  [s_prev | x_t] W_cat   (s_prev null: no spikes yet)
+//      backward: g_next W_rec^T          (WrT = W_rec^T)
+// written to part[z][B][N]; the epilogue kernels sum the parts in a fixed
+// order.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_bptt_part(const BpttDev p, const float* __restrict__ Bm,
+                                                   const float* s_prev, const float* __restrict__ x_t, int kc,
+                                                   float* __restrict__ part) {
+  __shared__ float As[2][64][kT64 + 4];  // row strides 68 and 80 words: the
+  __shared__ float Bs[2][kT64][80];      // matrix-core operand reads are 2-way in the 32 banks
+  const int col0 = 64 * blockIdx.x, row0 = 64 * blockIdx.y;
+  const int N = p.N, Nin = p.Nin, B = p.B, K = FWD ? N + Nin : N;
+  const int k0 = blockIdx.z * kc, k1 = min(K, k0 + kc);
   auto Aload = [&](int r, int k) -> float {
     const int b = row0 + r;
-    if (b >= B || k >= K) return 0.f;
+    if (b >= B || k >= k1) return 0.f;
+    if (!FWD) return s_prev[static_cast<size_t>(b) * N + k];  // g_next
     if (k < N) return s_prev ? s_prev[static_cast<size_t>(b) * N + k] : 0.f;
     return x_t[static_cast<size_t>(b) * Nin + (k - N)];
   };
   auto Bload = [&](int k, int c) -> float {
     const int j = col0 + c;
-    return (k < K && j < N) ? W[static_cast<size_t>(k) * N + j] : 0.f;
+    return (k < k1 && j < N) ? Bm[static_cast<size_t>(k) * N + j] : 0.f;
   };
-  const f32x4 acc = tile_product(K, Aload, Bload, As, Bs);
+  Acc64 acc;
+  if (FWD ? (s_prev || k1 > N) : true) {
+    acc = tile_product64(k0, k1, Aload, Bload, As, Bs);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc.v[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int col = col0 + 16 * wc + (lane & 15);
+  float* out = part + static_cast<size_t>(blockIdx.z) * B * N;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int b = row0 + 16 * wr + 4 * (lane >> 4) + r;
-    bool spike = false;
-    if (b < B && col < N) {
-      const size_t e = static_cast<size_t>(b) * N + col;
-      const float vp = V_prev ? V_prev[e] : p.reset;
-      const float U = leak_clamped(vp, p.reset, p.leak) + acc[r];
-      float s;
-      if (p.relaxed) {
-        const float xx = U - p.theta;
-        s = 0.5f + xx / (1.f + p.slope * fabsf(xx));
-      } else {
-        s = U > p.theta ? 1.f : 0.f;
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = row0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
+        const int col = col0 + 32 * wc + 16 * j + (lane & 15);
+        if (b < B && col < N) out[static_cast<size_t>(b) * N + col] = acc.v[i][j][r];
       }
-      spike = s != 0.f;
-      s_out[e] = s;
-      V_out[e] = (1.f - s) * U + s * p.reset;
-      counts[e] += s;
-      if (U_keep) U_keep[e] = U;
+}
+
+// Forward epilogue of step t, one thread per (trial, neuron), element
+// e = b N + n: U = leak(V_prev) + sum of the parts, the spike (hard or
+// relaxed), V, the spike count; optionally U and bit-packed spikes (64
+// consecutive elements per wave ballot, written as 16-bit pieces) and the A
+// row [s_prev | x_t] of the step (A_keep [B][N + Nin]).
+__global__ __launch_bounds__(256) void k_bptt_fwd_epi(const BpttDev p, const float* __restrict__ part, int nparts,
+                                                      const float* s_prev, const float* __restrict__ x_t,
+                                                      const float* V_prev, float* s_out, float* V_out, float* counts,
+                                                      float* U_keep, float* A_keep, uint16_t* bits_out) {
+  const size_t total = static_cast<size_t>(p.B) * p.N;
+  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  bool spike = false;
+  if (e < total) {
+    float acc = 0.f;
+    for (int z = 0; z < nparts; ++z) acc += part[static_cast<size_t>(z) * total + e];
+    const float vp = V_prev ? V_prev[e] : p.reset;
+    const float U = leak_clamped(vp, p.reset, p.leak) + acc;
+    float s;
+    if (p.relaxed) {
+      const float xx = U - p.theta;
+      s = 0.5f + xx / (1.f + p.slope * fabsf(xx));
+    } else {
+      s = U > p.theta ? 1.f : 0.f;
     }
-    if (bits_out) {
-      const uint64_t m = __ballot(spike);
-      // lanes (lane & 15) == 0 hold rows 4 (lane/16) + r: 16 spike bits each
-      if ((lane & 15) == 0 && b < B && col < N)
-        bits_out[(static_cast<size_t>(b) * N + col) / 16] = static_cast<uint16_t>(m >> (16 * (lane >> 4)));
-    }
+    spike = s != 0.f;
+    s_out[e] = s;
+    V_out[e] = (1.f - s) * U + s * p.reset;
+    counts[e] += s;
+    if (U_keep) U_keep[e] = U;
   }
-  if (A_keep) {  // the A rows of this step, for the weight gradient
-    for (int i = threadIdx.x; i < 32 * 32; i += 256) {
-      const int r = i >> 5, c = i & 31;
-      const int b = row0 + r;
-      if (b >= B) continue;
-      for (int k = col0 + c; k < K; k += 32 * gridDim.x) A_keep[static_cast<size_t>(b) * K + k] = Aload(r, k);
+  if (bits_out) {
+    const uint64_t m = __ballot(spike);
+    const int lane = threadIdx.x & 63;
+    if ((lane & 15) == 0 && e < total) bits_out[e / 16] = static_cast<uint16_t>(m >> lane);
+  }
+  if (A_keep) {  // A row of this step: K = N + Nin entries per trial
+    const int K = p.N + p.Nin;
+    const size_t totalA = static_cast<size_t>(p.B) * K;
+    for (size_t i = e; i < totalA; i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+      const size_t b = i / K, k = i - b * K;
+      A_keep[i] = k < static_cast<size_t>(p.N) ? (s_prev ? s_prev[b * p.N + k] : 0.f) : x_t[b * p.Nin + (k - p.N)];
     }
   }
 }
 
-// Backward step t: g_out = (dcount + g_next W_rec^T) sigma'(U_t - theta)
+// Backward epilogue of step t: g_out = (dcount + sum of the parts) sigma'(U_t - theta)
 //                  + [|V_t - r| > lambda] g_next ((1 - s_t) + (r - U_t) sigma')
-// WrT = W_rec^T [N][N]; g_next null at the last step (zero).
-__global__ __launch_bounds__(256) void k_bptt_backward(const BpttDev p, const float* __restrict__ WrT,
-                                                       const float* g_next, const float* __restrict__ dcount,
-                                                       const float* __restrict__ U_t, const float* __restrict__ V_t,
-                                                       const float* __restrict__ s_t, float* g_out) {
-  __shared__ float As[2][32][kTileK + 4];  // row stride 132 and 48 words: the
-  __shared__ float Bs[2][kTileK][48];      // matrix-core operand reads are 2-way in the 32 banks
-  const int col0 = 32 * blockIdx.x, row0 = 32 * blockIdx.y;
-  const int N = p.N, B = p.B;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  if (g_next) {
-    auto Aload = [&](int r, int k) -> float {
-      const int b = row0 + r;
-      return (b < B && k < N) ? g_next[static_cast<size_t>(b) * N + k] : 0.f;
-    };
-    auto Bload = [&](int k, int c) -> float {
-      const int j = col0 + c;
-      return (k < N && j < N) ? WrT[static_cast<size_t>(k) * N + j] : 0.f;
-    };
-    acc = tile_product(N, Aload, Bload, As, Bs);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int col = col0 + 16 * wc + (lane & 15);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int b = row0 + 16 * wr + 4 * (lane >> 4) + r;
-    if (b >= B || col >= N) continue;
-    const size_t e = static_cast<size_t>(b) * N + col;
-    const float U = U_t[e], V = V_t[e], s = s_t[e];
-    const float sg = surrogate_grad(U - p.theta, p.slope);
-    const float gn = g_next ? g_next[e] : 0.f;
-    const float gv = fabsf(V - p.reset) > p.leak ? gn : 0.f;
-    g_out[e] = (dcount[e] + acc[r]) * sg + gv * ((1.f - s) + (p.reset - U) * sg);
-  }
+// (nparts = 0: g_next is zero, the last step).
+__global__ __launch_bounds__(256) void k_bptt_bwd_epi(const BpttDev p, const float* __restrict__ part, int nparts,
+                                                      const float* g_next, const float* __restrict__ dcount,
+                                                      const float* __restrict__ U_t, const float* __restrict__ V_t,
+                                                      const float* __restrict__ s_t, float* g_out) {
+  const size_t total = static_cast<size_t>(p.B) * p.N;
+  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  float acc = 0.f;
+  for (int z = 0; z < nparts; ++z) acc += part[static_cast<size_t>(z) * total + e];
+  const float U = U_t[e], V = V_t[e], s = s_t[e];
+  const float sg = surrogate_grad(U - p.theta, p.slope);
+  const float gn = g_next ? g_next[e] : 0.f;
+  const float gv = fabsf(V - p.reset) > p.leak ? gn : 0.f;
+  g_out[e] = (dcount[e] + acc) * sg + gv * ((1.f - s) + (p.reset - U) * sg);
 }
 
 // dW[K][N] += A^T G over M rows: A [M][K], G [M][N] (row-major).
 __global__ __launch_bounds__(256) void k_bptt_wgrad(int M, int K, int N, const float* __restrict__ A,
                                                     const float* __restrict__ G, float* dW) {
-  __shared__ float As[2][32][kTileK + 4];  // row stride 132 and 48 words: the
-  __shared__ float Bs[2][kTileK][48];      // matrix-core operand reads are 2-way in the 32 banks
-  const int col0 = 32 * blockIdx.x, row0 = 32 * blockIdx.y;  // columns of dW (j), rows of dW (k)
+  __shared__ float As[2][64][kT64 + 4];  // row strides 68 and 80 words: the
+  __shared__ float Bs[2][kT64][80];      // matrix-core operand reads are 2-way in the 32 banks
+  const int col0 = 64 * blockIdx.x, row0 = 64 * blockIdx.y;  // columns of dW (j), rows of dW (k)
   auto Aload = [&](int r, int m) -> float {  // (A^T)[row0 + r][m]
     const int k = row0 + r;
     return (k < K && m < M) ? A[static_cast<size_t>(m) * K + k] : 0.f;
@@ -214,15 +239,19 @@ __global__ __launch_bounds__(256) void k_bptt_wgrad(int M, int K, int N, const f
     const int j = col0 + c;
     return (m < M && j < N) ? G[static_cast<size_t>(m) * N + j] : 0.f;
   };
-  const f32x4 acc = tile_product(M, Aload, Bload, As, Bs);
+  const Acc64 acc = tile_product64(0, M, Aload, Bload, As, Bs);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int col = col0 + 16 * wc + (lane & 15);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int k = row0 + 16 * wr + 4 * (lane >> 4) + r;
-    if (k < K && col < N) dW[static_cast<size_t>(k) * N + col] += acc[r];
-  }
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = row0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
+        const int col = col0 + 32 * wc + 16 * jj + (lane & 15);
+        if (k < K && col < N) dW[static_cast<size_t>(k) * N + col] += acc.v[i][jj][r];
+      }
 }
 
 __global__ void k_transpose(const float* __restrict__ src, float* dst, int n) {
@@ -261,8 +290,20 @@ __global__ void k_fill(float* p, float v, size_t count) {
 namespace {
 
 struct WsLayout {
-  size_t spikes, vckpt, sbuf, vbuf, useg, vseg, sseg, gseg, aseg, wrt, carry, sprev, junk, total;
+  size_t spikes, vckpt, sbuf, vbuf, useg, vseg, sseg, gseg, aseg, wrt, carry, sprev, junk, part, total;
 };
+
+// K split of a per-step product over about two workgroups per compute unit
+// (tiles of 64 x 64 outputs): chunk length kc (a multiple of kT64), parts.
+struct KSplit {
+  int kc, parts;
+};
+KSplit ksplit(int K, int N, int B) {
+  const int tiles = ((N + 63) / 64) * ((B + 63) / 64);
+  const int want = std::max(1, std::min(16, (512 + tiles - 1) / tiles));
+  const int kc = std::max(kT64, (K + want * kT64 - 1) / (want * kT64) * kT64);
+  return {kc, (K + kc - 1) / kc};
+}
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -286,6 +327,9 @@ WsLayout ws_layout(const sn_bptt_desc& d) {
   L.carry = take(bn);
   L.sprev = take(bn);
   L.junk = take(bn);
+  const int pf = ksplit(static_cast<int>(N + Nin), static_cast<int>(N), static_cast<int>(B)).parts;
+  const int pb = ksplit(static_cast<int>(N), static_cast<int>(N), static_cast<int>(B)).parts;
+  L.part = take(static_cast<size_t>(std::max(pf, pb)) * bn);
   L.total = o;
   return L;
 }
@@ -329,7 +373,10 @@ hipError_t bptt_forward(const sn_bptt_desc& d, const float* W, const float* x, f
   const BpttDev p = dev_of(d);
   const int N = d.n_neurons, Nin = d.n_inputs, B = d.n_trials, T = d.n_steps, K = d.checkpoint_every;
   const size_t bn = static_cast<size_t>(B) * N;
-  const dim3 grid((N + 31) / 32, (B + 31) / 32);
+  const dim3 grid64((N + 63) / 64, (B + 63) / 64);
+  const dim3 epi(static_cast<unsigned>((bn + 255) / 256));
+  const KSplit kf = ksplit(N + Nin, N, B);
+  float* part = at<float>(ws, L.part);
   SN_TRY(fill(counts, 0.f, bn, s));
   for (int t = 0; t < T; ++t) {
     float* s_out = at<float>(ws, L.sbuf) + (t & 1) * bn;
@@ -337,8 +384,12 @@ hipError_t bptt_forward(const sn_bptt_desc& d, const float* W, const float* x, f
     const float* s_prev = t > 0 ? at<float>(ws, L.sbuf) + ((t - 1) & 1) * bn : nullptr;
     const float* v_prev = t > 0 ? at<float>(ws, L.vbuf) + ((t - 1) & 1) * bn : nullptr;
     uint16_t* bits = d.relaxed ? nullptr : at<uint16_t>(ws, L.spikes) + static_cast<size_t>(t) * bn / 16;
-    hipLaunchKernelGGL(k_bptt_forward, grid, dim3(256), 0, s, p, W, s_prev, x + static_cast<size_t>(t) * B * Nin,
-                       v_prev, s_out, v_out, counts, static_cast<float*>(nullptr), static_cast<float*>(nullptr), bits);
+    const float* x_t = x + static_cast<size_t>(t) * B * Nin;
+    hipLaunchKernelGGL(k_bptt_part<true>, dim3(grid64.x, grid64.y, kf.parts), dim3(256), 0, s, p, W, s_prev, x_t,
+                       kf.kc, part);
+    SN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_bptt_fwd_epi, epi, dim3(256), 0, s, p, part, kf.parts, s_prev, x_t, v_prev, s_out, v_out,
+                       counts, static_cast<float*>(nullptr), static_cast<float*>(nullptr), bits);
     SN_TRY(hipGetLastError());
     if (d.relaxed)
       SN_TRY(hipMemcpyAsync(at<float>(ws, L.spikes) + static_cast<size_t>(t) * bn, s_out, bn * sizeof(float),
@@ -358,7 +409,10 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
   const int N = d.n_neurons, Nin = d.n_inputs, B = d.n_trials, T = d.n_steps, K = d.checkpoint_every;
   const int KA = N + Nin;
   const size_t bn = static_cast<size_t>(B) * N;
-  const dim3 grid((N + 31) / 32, (B + 31) / 32);
+  const dim3 grid64((N + 63) / 64, (B + 63) / 64);
+  const dim3 epi(static_cast<unsigned>((bn + 255) / 256));
+  const KSplit kf = ksplit(KA, N, B), kb = ksplit(N, N, B);
+  float* part = at<float>(ws, L.part);
   float* wrt = at<float>(ws, L.wrt);
   hipLaunchKernelGGL(k_transpose, dim3((N + 31) / 32, (N + 31) / 32), dim3(32, 8), 0, s, W, wrt, N);
   SN_TRY(hipGetLastError());
@@ -385,9 +439,13 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
       const size_t i = static_cast<size_t>(t - t0);
       float* s_out = at<float>(ws, L.sseg) + i * bn;
       float* v_out = at<float>(ws, L.vseg) + i * bn;
-      hipLaunchKernelGGL(k_bptt_forward, grid, dim3(256), 0, s, p, W, s_prev, x + static_cast<size_t>(t) * B * Nin,
-                         v_prev, s_out, v_out, at<float>(ws, L.junk), at<float>(ws, L.useg) + i * bn,
-                         at<float>(ws, L.aseg) + i * B * KA, static_cast<uint16_t*>(nullptr));
+      const float* x_t = x + static_cast<size_t>(t) * B * Nin;
+      hipLaunchKernelGGL(k_bptt_part<true>, dim3(grid64.x, grid64.y, kf.parts), dim3(256), 0, s, p, W, s_prev, x_t,
+                         kf.kc, part);
+      SN_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_bptt_fwd_epi, epi, dim3(256), 0, s, p, part, kf.parts, s_prev, x_t, v_prev, s_out, v_out,
+                         at<float>(ws, L.junk), at<float>(ws, L.useg) + i * bn, at<float>(ws, L.aseg) + i * B * KA,
+                         static_cast<uint16_t*>(nullptr));
       SN_TRY(hipGetLastError());
       s_prev = s_out;
       v_prev = v_out;
@@ -397,14 +455,20 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
       const size_t i = static_cast<size_t>(t - t0);
       const float* g_next = nullptr;
       if (t < T - 1) g_next = (t == t1 - 1) ? at<float>(ws, L.carry) : at<float>(ws, L.gseg) + (i + 1) * bn;
-      hipLaunchKernelGGL(k_bptt_backward, grid, dim3(256), 0, s, p, wrt, g_next, dcounts, at<float>(ws, L.useg) + i * bn,
-                         at<float>(ws, L.vseg) + i * bn, at<float>(ws, L.sseg) + i * bn, at<float>(ws, L.gseg) + i * bn);
+      if (g_next) {
+        hipLaunchKernelGGL(k_bptt_part<false>, dim3(grid64.x, grid64.y, kb.parts), dim3(256), 0, s, p, wrt, g_next,
+                           static_cast<const float*>(nullptr), kb.kc, part);
+        SN_TRY(hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_bptt_bwd_epi, epi, dim3(256), 0, s, p, part, g_next ? kb.parts : 0, g_next, dcounts,
+                         at<float>(ws, L.useg) + i * bn, at<float>(ws, L.vseg) + i * bn, at<float>(ws, L.sseg) + i * bn,
+                         at<float>(ws, L.gseg) + i * bn);
       SN_TRY(hipGetLastError());
     }
     SN_TRY(hipMemcpyAsync(at<float>(ws, L.carry), at<float>(ws, L.gseg), bn * sizeof(float), hipMemcpyDeviceToDevice, s));
     // dW_cat += A_seg^T G_seg
     const int M = (t1 - t0) * B;
-    hipLaunchKernelGGL(k_bptt_wgrad, dim3((N + 31) / 32, (KA + 31) / 32), dim3(256), 0, s, M, KA, N,
+    hipLaunchKernelGGL(k_bptt_wgrad, dim3((N + 63) / 64, (KA + 63) / 64), dim3(256), 0, s, M, KA, N,
                        at<float>(ws, L.aseg), at<float>(ws, L.gseg), dW);
     SN_TRY(hipGetLastError());
   }
