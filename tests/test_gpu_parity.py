@@ -119,6 +119,38 @@ def test_persist_slices(gpu, oracle, slices):
     assert_parity(net, res, s, V, r, f"slices={slices}")
 
 
+def hub_net(seed, n=1536, nnz=60_000, hubs=5, hub_frac=0.3, steps=80, max_delay=6):
+    """Skewed in-degrees: a fraction of all synapses lands on a few hub posts,
+    so their groups overflow the lane-owned rows (overflow records are added
+    atomically) while the other posts fill rows with zero-weight fillers."""
+    g = np.random.default_rng(seed)
+    pre = g.integers(0, n, nnz).astype(np.int32)
+    post = g.integers(0, n, nnz).astype(np.int32)
+    hub_ids = g.choice(n, hubs, replace=False)
+    to_hub = g.random(nnz) < hub_frac
+    post[to_hub] = hub_ids[g.integers(0, hubs, int(to_hub.sum()))]
+    w = (g.integers(-8, 9, nnz) / 64.0).astype(np.float32)
+    d = g.integers(1, max_delay + 1, nnz).astype(np.uint8)
+    base = wl.large_sparse(seed, n=n, p=0.0, steps=steps, max_delay=max_delay, drive_frac=0.2, drive_p=0.2)
+    return dataclasses.replace(base, name=f"hubs_{seed}", pre=pre, post=post, weight=w, delay=d)
+
+
+@pytest.mark.parametrize("slices", [1, 2, 3, 6, 24])
+def test_hub_overflow_and_delivery_modes(gpu, oracle, slices):
+    """Hub posts (overflow records) under slice counts that put the persistent
+    kernel in each way of sharing groups among waves (one slice of 24 groups:
+    contiguous ranges; 2, 3: own groups or slots; 6, 24: slots), plus the
+    per-step and single-workgroup paths."""
+    net = hub_net(40 + slices)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "persist", chunks=[30, 50], slices=slices)
+    assert_parity(net, res, s, V, r, f"persist slices={slices}")
+    if slices == 1:
+        for path in ("step", "small", "push"):
+            s, V, r, used = simulate(gpu, net, path, chunks=[30, 50])
+            assert_parity(net, res, s, V, r, path)
+
+
 def test_persist_global_ring(gpu, oracle):
     """A spike ring too large for LDS (N = 40,000, D = 64): bits come from the
     tagged mailbox ring in global memory.  A request for one slice is raised
