@@ -44,6 +44,9 @@ def _bind(lib):
     lib.or_bptt.restype = ctypes.c_int
     lib.or_bptt.argtypes = [_I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
+    lib.or_lif_stdp.restype = ctypes.c_int
+    lib.or_lif_stdp.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                _I32, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.or_lif_dense.restype = ctypes.c_int
     lib.or_lif_dense.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P, _P, ctypes.c_int]
@@ -115,6 +118,47 @@ class Oracle:
         if rc not in (OR_OK, OR_NONEXACT):
             raise ValueError(f"oracle rejected the input (status {rc})")
         return OracleResult(spikes, V, ref, rc == OR_OK)
+
+
+@dataclasses.dataclass
+class StdpResult:
+    spikes: np.ndarray      # uint8 [T][N]
+    V: np.ndarray           # float64 [N]
+    ref: np.ndarray         # int32 [N]
+    weight: np.ndarray      # float64 [nnz], after the last step, input order
+    exact: bool
+
+
+def _stdp(self, net, window, ltp, ltd, w_min, w_max, steps=None) -> StdpResult:
+    """One trial of ``net`` with the plasticity rule of or_lif_stdp; ltp and
+    ltd are sequences of ``window`` amplitudes."""
+    T = net.steps if steps is None else int(steps)
+    ext = np.ascontiguousarray(net.ext[0, :T], dtype=np.uint8)
+    N = net.n
+    th, lk, rs, rf, am = self._params(net)
+    pre = np.ascontiguousarray(net.pre, dtype=np.int32)
+    post = np.ascontiguousarray(net.post, dtype=np.int32)
+    w = np.array(net.weight, dtype=np.float64)
+    d = np.ascontiguousarray(net.delay, dtype=np.int32)
+    # entries past the window are never read; they hold a sentinel so that a
+    # rule reading past its window changes the result
+    lp = np.full(16, 0.5)
+    lm = np.full(16, 0.5)
+    lp[:window] = ltp[:window]
+    lm[:window] = ltd[:window]
+    spikes = np.zeros((T, N), np.uint8)
+    V = np.zeros(N)
+    ref = np.zeros(N, np.int32)
+    P = self._ptr
+    rc = self.lib.or_lif_stdp(N, int(net.max_delay), T, P(th), P(lk), P(rs), P(rf), P(am), pre.shape[0], P(pre),
+                              P(post), P(w), P(d), P(ext), P(spikes), P(V), P(ref), int(window), P(lp), P(lm),
+                              float(w_min), float(w_max), 1)
+    if rc not in (OR_OK, OR_NONEXACT):
+        raise ValueError(f"oracle rejected the input (status {rc})")
+    return StdpResult(spikes, V, ref, w, rc == OR_OK)
+
+
+Oracle.stdp = _stdp
 
 
 @dataclasses.dataclass

@@ -165,6 +165,95 @@ int or_lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
 }
 
 /*
+ * Spike-timing-dependent plasticity on the synapse list.  §2.1 names STDP as
+ * the learning of the matrix mode but gives no rule, window or constants, so
+ * the rule below is a chosen one (parity of the rule itself is unpinned by the
+ * paper); it keeps every weight on the 2^-6 grid when the tables are on it.
+ * One trial.  A spike of pre-neuron i at step tau arrives at post-neuron j at
+ * t_a = tau + d.  After the update of step t (the new weights act from step
+ * t + 1), for every synapse i->j of delay d:
+ *   - potentiation, if j spikes at t: the latest arrival t_a <= t with
+ *     t - t_a < W adds ltp[t - t_a];
+ *   - depression, if a spike of i arrives at t (i spiked at t - d): the latest
+ *     spike of j at t_post < t with t - t_post <= W subtracts ltd[t - t_post - 1];
+ *   - then w = min(max(w, w_min), w_max).
+ * Each synapse's change depends on spike times only, so the order in which
+ * synapses are visited does not matter.  w is updated in place.
+ */
+int or_lif_stdp(int32_t N, int32_t D, int32_t T,
+                const double* theta, const double* leak, const double* reset,
+                const int32_t* refractory, const double* amplitude,
+                int64_t nnz, const int32_t* pre, const int32_t* post,
+                double* w, const int32_t* delay,
+                const uint8_t* ext, uint8_t* spikes,
+                double* V, int32_t* ref, int32_t W, const double* ltp, const double* ltd,
+                double w_min, double w_max, int check_exact) {
+    if (N < 1 || D < 1 || T < 0 || nnz < 0 || W < 1 || W > 16 || !(w_min <= w_max)) return OR_EINVAL;
+    for (int64_t k = 0; k < nnz; ++k) {
+        if (pre[k] < 0 || pre[k] >= N || post[k] < 0 || post[k] >= N) return OR_EINVAL;
+        if (delay[k] < 1 || delay[k] > D) return OR_EINVAL;
+        if (!isfinite(w[k])) return OR_EINVAL;
+    }
+    int exact = 1;
+    if (check_exact) {
+        if (!check_params(N, theta, leak, reset, refractory, amplitude)) exact = 0;
+        for (int64_t k = 0; k < nnz; ++k)
+            if (!on_grid(w[k])) exact = 0;
+        for (int32_t k = 0; k < W; ++k)
+            if (!on_grid(ltp[k]) || !on_grid(ltd[k])) exact = 0;
+        if (!on_grid(w_min) || !on_grid(w_max)) exact = 0;
+    }
+    double* in_abs = (double*)malloc((size_t)N * sizeof(double));
+    double* U = (double*)malloc((size_t)N * sizeof(double));
+    if (!in_abs || !U) { free(in_abs); free(U); return OR_ENOMEM; }
+    for (int32_t j = 0; j < N; ++j) { V[j] = reset[j]; ref[j] = 0; }
+
+    for (int32_t t = 0; t < T; ++t) {
+        for (int32_t j = 0; j < N; ++j) in_abs[j] = 0.0;
+        for (int64_t k = 0; k < nnz; ++k) in_abs[post[k]] += fabs(w[k]);
+        /* steps 1-6 of the model, as in or_lif_sparse */
+        for (int32_t j = 0; j < N; ++j) {
+            U[j] = apply_leak(V[j], reset[j], leak[j]);
+            if (check_exact && !(fabs(U[j]) + in_abs[j] + fabs(amplitude[j]) < EXACT_LIMIT)) exact = 0;
+        }
+        for (int64_t k = 0; k < nnz; ++k) {
+            int32_t src_t = t - delay[k];
+            if (src_t >= 0 && spikes[(size_t)src_t * N + pre[k]]) U[post[k]] += w[k];
+        }
+        for (int32_t j = 0; j < N; ++j)
+            if (ext[(size_t)t * N + j]) U[j] += amplitude[j];
+        for (int32_t j = 0; j < N; ++j)
+            spikes[(size_t)t * N + j] =
+                (uint8_t)fire_and_reset(U[j], theta[j], reset[j], refractory[j], &V[j], &ref[j]);
+        /* plasticity from the spike times up to and including t */
+        for (int64_t k = 0; k < nnz; ++k) {
+            const int32_t i = pre[k], j = post[k], d = delay[k];
+            double change = 0.0;
+            if (spikes[(size_t)t * N + j]) {
+                for (int32_t lag = 0; lag < W; ++lag) {   /* arrival at t - lag */
+                    int32_t tau = t - lag - d;
+                    if (tau < 0) break;
+                    if (spikes[(size_t)tau * N + i]) { change += ltp[lag]; break; }
+                }
+            }
+            if (t - d >= 0 && spikes[(size_t)(t - d) * N + i]) {
+                for (int32_t lag = 1; lag <= W; ++lag) {  /* post spike at t - lag */
+                    if (t - lag < 0) break;
+                    if (spikes[(size_t)(t - lag) * N + j]) { change -= ltd[lag - 1]; break; }
+                }
+            }
+            if (change != 0.0 || w[k] < w_min || w[k] > w_max) {
+                double x = w[k] + change;
+                w[k] = x < w_min ? w_min : (x > w_max ? w_max : x);
+            }
+        }
+    }
+    free(in_abs);
+    free(U);
+    return exact ? OR_OK : OR_NONEXACT;
+}
+
+/*
  * Dense weight matrix W [N][N] (row = pre, column = post, §2.1), every synapse
  * of delay 1: the literal matrix form "spike vector of the previous step times
  * the weight matrix".  Same state layout as or_lif_sparse.
