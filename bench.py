@@ -14,6 +14,8 @@ device memory.  Workloads:
                           T = 1000, matrix cores
   uneven_batch            512 independent nets, N 50..5000, T = 500: one
                           batched persistent launch vs one run per net
+  large_sparse_stdp       large_sparse with the plasticity rule on (window 8,
+                          per-step path): simulation + weight updates
   bptt                    surrogate-gradient training step of a recurrent
                           layer: N = 2048, 256 inputs, 128 trials, T = 200
                           (forward + backward through time), FP32 matrix cores
@@ -89,8 +91,18 @@ def measured_traffic(summary: str, source: str):
             "time_steps_per_launch": int(vals["time_steps_per_launch"]), "source": f"profiles/{summary}"}
 
 
+# plasticity rule of the large_sparse_stdp workload (amplitudes k/64)
+STDP_WINDOW = 8
+STDP_LTP = [16 / 64, 8 / 64, 4 / 64, 2 / 64, 1 / 64, 1 / 64, 1 / 64, 1 / 64]
+STDP_LTD = [12 / 64, 6 / 64, 3 / 64, 2 / 64, 1 / 64, 1 / 64, 1 / 64, 1 / 64]
+STDP_CLIP = (-0.5, 1.0)
+
+
 def bench_single(args, net, kind):
-    """One net (possibly many trials): reset + run(T) per benchmark step."""
+    """One net (possibly many trials): reset + run(T) per benchmark step.
+    kind "stdp": plasticity on; the weights keep learning across the timed
+    runs, and a last run from the loaded weights is checked against the
+    oracle."""
     from paper_2305_02510_amd import Network
     T = net.steps
     t_setup = time.perf_counter()
@@ -98,7 +110,9 @@ def bench_single(args, net, kind):
     g.synchronize()
     setup_s = time.perf_counter() - t_setup
     tuned = None
-    if args.path == "autotune":  # the library's autotuner picks path and slice count
+    if kind == "stdp":
+        g.set_stdp(STDP_WINDOW, STDP_LTP, STDP_LTD, *STDP_CLIP)  # runs on the per-step path
+    elif args.path == "autotune":  # the library's autotuner picks path and slice count
         tuned = g.autotune(min(T, 128))
     else:
         g.set_path(args.path)
@@ -108,6 +122,10 @@ def bench_single(args, net, kind):
         g.run(T)
 
     ms, wall = timed(one_run, g.stream, args.warmup, args.steps)
+    if kind == "stdp":  # the checked run starts from the loaded weights (setup, untimed)
+        g.load_weights_delays(net.pre, net.post, net.weight, net.delay)
+        one_run()
+        weights = g.read_weights()
     raster = g.read_raster(0, T)
     V, ref = g.read_state()
     path = g.progress[1]
@@ -139,6 +157,8 @@ def bench_single(args, net, kind):
         achieved = bytes_step / sec_per_tstep / 1e9
         kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)", "step": "k_step",
                   "push": "k_push"}.get(path, path)
+        if kind == "stdp":
+            kernel = "k_step + k_stdp (per step)"
         traffic = None
         if path == "persist" and net.name.startswith("large_sparse_n10000") and (tuned is None or tuned[1] == 0):
             # counters taken on the default slice plan
@@ -156,7 +176,11 @@ def bench_single(args, net, kind):
         orc = oracle.default()
         trials = list(range(min(net.trials, args.cpu_trials)))
         c0 = time.perf_counter()
-        res = orc.run_dense(net, trials=trials) if kind == "dense" else orc.run_sparse(net, trials=trials)
+        if kind == "stdp":
+            res = orc.stdp(net, STDP_WINDOW, STDP_LTP, STDP_LTD, *STDP_CLIP)
+            res.spikes, res.V, res.ref = res.spikes[None], res.V[None], res.ref[None]
+        else:
+            res = orc.run_dense(net, trials=trials) if kind == "dense" else orc.run_sparse(net, trials=trials)
         csec = time.perf_counter() - c0
         ev_cpu = events_of(res.spikes, net.out_degree())
         out["cpu_baseline"] = {
@@ -166,7 +190,8 @@ def bench_single(args, net, kind):
                       f"{csec:.2f} s single-threaded"}
         out["parity_bit_exact"] = bool(
             np.array_equal(raster[trials], res.spikes) and np.array_equal(V[trials].astype(np.float64), res.V)
-            and np.array_equal(ref[trials].astype(np.int32), res.ref))
+            and np.array_equal(ref[trials].astype(np.int32), res.ref)
+            and (kind != "stdp" or np.array_equal(weights.astype(np.float64), res.weight)))
         out["parity_sample"] = f"trials {trials}"
     return out
 
@@ -312,7 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_sparse",
-                    choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch", "bptt"])
+                    choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch", "bptt",
+                             "large_sparse_stdp"])
     ap.add_argument("--path", default="autotune",
                     help="autotune (sn_autotune picks), auto (built-in heuristic) or a path name")
     ap.add_argument("--cpu-trials", type=int, default=2)
@@ -359,11 +385,12 @@ def main():
                 f"p 0.005..0.2 (total {r['total_synapses']} synapses), D 1..16, T=500")
         cfg = {"workload": desc, "nets": r["nets"], "time_steps_per_run": 500}
     else:
-        net = wl.by_name(args.workload)
-        kind = "dense" if args.workload == "dense_trials" else "sparse"
+        net = wl.by_name("large_sparse" if args.workload == "large_sparse_stdp" else args.workload)
+        kind = {"dense_trials": "dense", "large_sparse_stdp": "stdp"}.get(args.workload, "sparse")
         r = bench_single(args, net, kind)
         cfg = {"workload": f"{net.name}: N={net.n}, nnz={net.nnz}, D={net.max_delay}, T={net.steps}, "
-                           f"trials={net.trials}", "time_steps_per_run": net.steps, "trials": net.trials}
+                           f"trials={net.trials}" + (", STDP window 8" if kind == "stdp" else ""),
+               "time_steps_per_run": net.steps, "trials": net.trials}
     cfg["path"] = r["path"]
     if r.get("autotuned"):
         cfg["autotuned"] = {"path": r["autotuned"][0], "slices": r["autotuned"][1]}

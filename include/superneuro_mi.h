@@ -185,6 +185,39 @@ sn_status sn_set_path(sn_net* net, int32_t path);
  * Errors: SN_ERANGE. */
 sn_status sn_set_slices(sn_net* net, int32_t slices);
 
+/* Spike-timing-dependent plasticity (§2.1 names STDP as the learning of the
+ * matrix mode without a rule; this is a chosen, table-driven nearest-neighbour
+ * pair rule).  A spike of pre-neuron i at step tau arrives at j at tau + d.
+ * After the update of step t, for every synapse i -> j of delay d:
+ *   - if j spiked at t, the latest arrival t_a <= t with lag = t - t_a < window
+ *     adds ltp[lag];
+ *   - if a spike of i arrives at t, the latest spike of j at t - lag,
+ *     1 <= lag <= window, subtracts ltd[lag - 1];
+ *   - the weight is then clipped to [w_min, w_max].
+ * The new weights act from step t + 1.  With table entries and bounds that
+ * are multiples of 2^-6 the weights stay on that grid and runs stay exact. */
+typedef struct {
+  int32_t window;  /* 1..16 steps */
+  float ltp[16];   /* entries 0 .. window - 1 are used */
+  float ltd[16];
+  float w_min, w_max;
+} sn_stdp_desc;
+
+/* Turns plasticity on with the rule above (desc copied), or off (desc NULL).
+ * Needs a synapse list (not dense weights) and one trial.  While on, sn_run
+ * uses the per-step path (SN_PATH_AUTO or SN_PATH_STEP, else SN_ESTATE) and
+ * applies the rule after every step; the weights change in place
+ * (sn_reset_state does not restore them; sn_load_weights_delays does), and
+ * the event-driven path refuses to run (SN_ESTATE) until the weights are
+ * loaded again.  Errors: SN_ESTATE, SN_ERANGE (window, trials), SN_EINVAL
+ * (non-finite entries, w_min > w_max). */
+sn_status sn_set_stdp(sn_net* net, const sn_stdp_desc* desc);
+
+/* Copies the current synapse weights to w [nnz], in the order of the last
+ * sn_load_weights_delays (dense weights: their non-zero entries, row-major).
+ * Synchronizes the network's stream. */
+sn_status sn_read_weights(sn_net* net, float* w);
+
 /* Autotuner: times every strategy that can run this network (the
  * single-workgroup and multi-slice persistent kernels, the latter at several
  * slice counts, the per-step and event-driven paths; for dense weights the
@@ -196,7 +229,8 @@ sn_status sn_set_slices(sn_net* net, int32_t slices);
  * steps.  The state is reset (t = 0) before every trial and at the end.
  * *path_out / *slices_out (either may be NULL) receive the choice
  * (slices 0 = the default plan).  1 <= steps <= 4096, else SN_ERANGE; a
- * device error poisons the network as sn_run would. */
+ * device error poisons the network as sn_run would; SN_ESTATE while
+ * plasticity is on. */
 sn_status sn_autotune(sn_net* net, int32_t steps, int32_t* path_out, int32_t* slices_out);
 
 /* Reports the number of simulated steps so far (*t) and the strategy the

@@ -19,7 +19,7 @@ EXPORTS = [
     "sn_create_network", "sn_load_weights_delays", "sn_load_dense_weights", "sn_set_input_spikes",
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_autotune", "sn_get_progress", "sn_destroy_network",
-    "sn_last_error",
+    "sn_last_error", "sn_set_stdp", "sn_read_weights",
     "sn_batch_create", "sn_batch_run", "sn_batch_destroy",
     "sn_bptt_workspace_bytes", "sn_bptt_forward", "sn_bptt_backward",
 ]
@@ -41,6 +41,11 @@ class SnNetDesc(ctypes.Structure):
         ("reset_scalar", ctypes.c_float), ("amplitude_scalar", ctypes.c_float),
         ("refractory_scalar", ctypes.c_uint8),
     ]
+
+
+class SnStdpDesc(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("ltp", ctypes.c_float * 16), ("ltd", ctypes.c_float * 16),
+                ("w_min", ctypes.c_float), ("w_max", ctypes.c_float)]
 
 
 class SnError(RuntimeError):
@@ -76,6 +81,8 @@ def load():
         "sn_set_path": [P, I32],
         "sn_set_slices": [P, I32],
         "sn_autotune": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "sn_set_stdp": [P, ctypes.POINTER(SnStdpDesc)],
+        "sn_read_weights": [P, P],
         "sn_get_progress": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "sn_batch_create": [P, I32, ctypes.POINTER(P)],
         "sn_batch_run": [P, I32],

@@ -75,9 +75,16 @@ struct sn_net {
   // cached graph of per-step launches
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
-  int32_t graph_path = -1, graph_t0 = -1, graph_steps = -1;
+  int32_t graph_path = -1, graph_t0 = -1, graph_steps = -1, graph_stdp = -1;
   const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
   int32_t slices_req = 0;
+  // plasticity (sn_set_stdp): on, its arguments, a generation for the graph
+  // cache, and whether the event-driven records still hold the loaded weights
+  bool stdp_on = false;
+  StdpArgs stdp{};
+  int32_t stdp_gen = 0;
+  bool push_stale = false;
+  int64_t nnz_loaded = 0;
   uint64_t* mailbox = nullptr;  // [D + 1][B][2G] tagged spike words
   uint32_t* slice_flags = nullptr;  // [B][256][64]
   uint32_t* status = nullptr;
@@ -239,6 +246,11 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
         e = launch_dense_step(a, t0 + k, s);
       } else {
         e = launch_step(n->d, t0 + k, s);
+        if (e == hipSuccess && n->stdp_on) {
+          StdpArgs a = n->stdp;
+          a.n = n->d;
+          e = launch_stdp(a, t0 + k, s);
+        }
       }
       if (e != hipSuccess) return e;
     }
@@ -249,8 +261,9 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
     return SN_OK;
   }
   const void* key[4] = {n->d.raster, n->d.ext, n->d.recs, n->wt};
+  const int32_t stdp_key = n->stdp_on ? n->stdp_gen : 0;
   const bool hit = n->graph && n->graph_path == path && n->graph_t0 == t0 && n->graph_steps == steps &&
-                   std::equal(key, key + 4, n->graph_key);
+                   n->graph_stdp == stdp_key && std::equal(key, key + 4, n->graph_key);
   if (!hit) {
     if (n->graph) {
       SN_HIP(n, hipGraphExecDestroy(n->graph));
@@ -269,6 +282,7 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
     n->graph_path = path;
     n->graph_t0 = t0;
     n->graph_steps = steps;
+    n->graph_stdp = stdp_key;
     std::copy(key, key + 4, n->graph_key);
   }
   SN_HIP(n, hipGraphLaunch(n->graph, n->stream));
@@ -741,6 +755,9 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   st = upload_plan(n, n->persist, plan_persist(n->d, L, n->slices_req));
   if (st != SN_OK) return st;
   n->layout = std::move(L);
+  n->push_stale = false;
+  n->nnz_loaded = nnz;
+  n->stdp.recs = static_cast<Rec*>(n->recs);
   return SN_OK;
 }
 
@@ -804,6 +821,7 @@ sn_status sn_load_dense_weights(sn_net* n, const float* W, int32_t delay) {
   SN_HIP(n, hipStreamSynchronize(n->stream));
   SN_HIP(n, prepare_dense_kernel(kpad));
   n->dense_loaded = true;
+  n->stdp_on = false;
   return SN_OK;
 }
 
@@ -880,6 +898,13 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
   if (st != SN_OK) return st;
 
   int32_t path = n->path;
+  if (n->stdp_on) {  // plasticity runs with the per-step kernels
+    if (path != SN_PATH_AUTO && path != SN_PATH_STEP)
+      return fail(SN_ESTATE, "with plasticity on, only the per-step path runs (set SN_PATH_AUTO or SN_PATH_STEP)");
+    path = SN_PATH_STEP;
+  }
+  if (path == SN_PATH_PUSH && n->push_stale)
+    return fail(SN_ESTATE, "plasticity changed the weights: reload them before the event-driven path");
   if (path == SN_PATH_AUTO) {
     // one workgroup when its records and spike ring fit in LDS, otherwise one
     // launch per step
@@ -905,6 +930,7 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
       SN_HIP(n, prepare_step_kernel(n->d));
       st = run_per_step(n, SN_PATH_STEP, n->t, n_steps);
       if (st != SN_OK) return st;
+      if (n->stdp_on) n->push_stale = true;
       break;
     case SN_PATH_PUSH:
       st = run_push(n, n->t, n_steps);
@@ -986,11 +1012,58 @@ sn_status sn_read_state(sn_net* n, float* V, uint8_t* refractory_left) {
   return SN_OK;
 }
 
+sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (!desc) {
+    n->stdp_on = false;
+    return SN_OK;
+  }
+  if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_set_stdp");
+  if (n->dense_loaded) return fail(SN_ESTATE, "plasticity applies to synapse lists, not dense weights");
+  if (n->d.B != 1) return fail(SN_ERANGE, "plasticity needs one trial (got %d)", n->d.B);
+  if (desc->window < 1 || desc->window > 16) return fail(SN_ERANGE, "window %d outside [1, 16]", desc->window);
+  if (!std::isfinite(desc->w_min) || !std::isfinite(desc->w_max) || !(desc->w_min <= desc->w_max))
+    return fail(SN_EINVAL, "need finite w_min <= w_max");
+  for (int k = 0; k < desc->window; ++k)
+    if (!std::isfinite(desc->ltp[k]) || !std::isfinite(desc->ltd[k])) return fail(SN_EINVAL, "table entry %d is not finite", k);
+  StdpArgs a{};
+  a.n = n->d;
+  a.recs = static_cast<Rec*>(n->recs);
+  a.window = desc->window;
+  for (int k = 0; k < 16; ++k) {
+    a.ltp[k] = k < desc->window ? desc->ltp[k] : 0.f;
+    a.ltd[k] = k < desc->window ? desc->ltd[k] : 0.f;
+  }
+  a.w_min = desc->w_min == 0.f ? 0.f : desc->w_min;  // -0 would read as a filler mark
+  a.w_max = desc->w_max == 0.f ? 0.f : desc->w_max;
+  SN_HIP(n, prepare_stdp_kernel());
+  n->stdp = a;
+  n->stdp_on = true;
+  ++n->stdp_gen;
+  return SN_OK;
+}
+
+sn_status sn_read_weights(sn_net* n, float* w) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (!n->synapses_loaded) return fail(SN_ESTATE, "no synapses loaded");
+  if (n->nnz_loaded > 0 && !w) return fail(SN_EINVAL, "w must not be NULL");
+  std::vector<Rec> recs(n->layout.recs.size());
+  if (!recs.empty())
+    SN_HIP(n, hipMemcpyAsync(recs.data(), n->recs, recs.size() * sizeof(Rec), hipMemcpyDeviceToHost, n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));
+  for (size_t k = 0; k < recs.size(); ++k)
+    if (n->layout.src[k] >= 0) w[n->layout.src[k]] = recs[k].w;
+  return SN_OK;
+}
+
 sn_status sn_autotune(sn_net* n, int32_t steps, int32_t* path_out, int32_t* slices_out) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
   if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_autotune");
   if (steps < 1 || steps > 4096) return fail(SN_ERANGE, "steps %d outside [1, 4096]", steps);
+  if (n->stdp_on) return fail(SN_ESTATE, "plasticity would change the weights while timing: turn it off first");
   if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
   struct Cand {
     int32_t path, slices;

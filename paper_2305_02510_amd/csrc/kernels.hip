@@ -804,6 +804,103 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Plasticity after the update of step t (one trial; the rule of
+// sn_set_stdp): workgroup g visits the records of group g.  For a record
+// i -> j of delay d: if j spiked at t, the latest arrival of i at j within
+// the window (i spiked at t - d - lag, lag < W) adds ltp[lag]; if a spike of
+// i arrives at t (i spiked at t - d), the latest spike of j at t - lag,
+// 1 <= lag <= W, subtracts ltd[lag - 1]; then the weight is clipped to
+// [w_min, w_max].  Spike bits come from the raster rows (written by earlier
+// launches); fillers (weight -0.0) are left alone.  Every change is a
+// function of spike times only, so records are independent.
+// ---------------------------------------------------------------------------
+// RING: the raster rows t - D - W + 1 .. t the rule can look at are first
+// copied into LDS (rows before step 0 as zeros), else read from the raster.
+constexpr int kStdpThreads = 1024;
+constexpr int kStdpUnroll = 4;  // records per thread loaded together
+
+template <bool RING>
+__global__ __launch_bounds__(kStdpThreads) void k_stdp(const StdpArgs a, int t) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* rows = reinterpret_cast<uint64_t*>(smem);  // [D + W][G], row t - D - W + 1 + i at i
+  const DevNet& n = a.n;
+  const int g = blockIdx.x;
+  const int beg = n.gptr[g], end = n.gptr[g + 1];
+  const int first = t - n.D - a.window + 1;
+  if (RING) {
+    const int nrows = n.D + a.window;
+    for (int i = threadIdx.x; i < nrows * n.G; i += blockDim.x) {
+      const int r = i / n.G, w = i - r * n.G;
+      rows[i] = first + r >= 0 ? n.raster[row_word(n, first + r, 0, w)] : 0ull;
+    }
+    __syncthreads();
+  }
+  auto bit = [&](int tau, uint32_t neuron) -> uint32_t {
+    const int w = static_cast<int>(neuron >> 6);
+    const uint64_t word = RING ? rows[(tau - first) * n.G + w] : n.raster[row_word(n, tau, 0, w)];
+    return static_cast<uint32_t>(word >> (neuron & 63u)) & 1u;
+  };
+  const uint64_t post_word = n.raster[row_word(n, t, 0, g)];
+  for (int k0 = beg + static_cast<int>(threadIdx.x); k0 < end; k0 += kStdpUnroll * kStdpThreads) {
+    Rec rr[kStdpUnroll];
+#pragma unroll
+    for (int u = 0; u < kStdpUnroll; ++u) {
+      const int k = k0 + u * kStdpThreads;
+      rr[u] = k < end ? a.recs[k] : Rec{-0.f, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < kStdpUnroll; ++u) {
+    const int k = k0 + u * kStdpThreads;
+    const Rec r = rr[u];
+    if (k >= end || __float_as_uint(r.w) == 0x80000000u) continue;  // past the group, or a filler
+    const uint32_t pre = r.meta & 0xFFFFFu;
+    const int d = static_cast<int>((r.meta >> 20) & 63u) + 1;
+    const uint32_t pl = r.meta >> 26;
+    const uint32_t post = static_cast<uint32_t>(g) * kGroup + pl;
+    float change = 0.f;
+    if ((post_word >> pl) & 1ull) {
+      for (int lag = 0; lag < a.window; ++lag) {
+        const int tau = t - lag - d;
+        if (tau < 0) break;
+        if (bit(tau, pre)) {
+          change += a.ltp[lag];
+          break;
+        }
+      }
+    }
+    if (t - d >= 0 && bit(t - d, pre)) {
+      for (int lag = 1; lag <= a.window; ++lag) {
+        if (t - lag < 0) break;
+        if (bit(t - lag, post)) {
+          change -= a.ltd[lag - 1];
+          break;
+        }
+      }
+    }
+    const float w = fminf(fmaxf(r.w + change, a.w_min), a.w_max);
+    if (__float_as_uint(w) != __float_as_uint(r.w)) a.recs[k].w = w;
+    }
+  }
+}
+
+constexpr size_t kStdpRingLimit = 64 * 1024;
+
+hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s) {
+  const size_t ring = static_cast<size_t>(a.n.D + a.window) * a.n.G * sizeof(uint64_t);
+  if (ring <= kStdpRingLimit) {
+    hipLaunchKernelGGL(k_stdp<true>, dim3(a.n.G), dim3(kStdpThreads), ring, s, a, t);
+  } else {
+    hipLaunchKernelGGL(k_stdp<false>, dim3(a.n.G), dim3(kStdpThreads), 0, s, a, t);
+  }
+  return hipGetLastError();
+}
+
+hipError_t prepare_stdp_kernel() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stdp<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(kStdpRingLimit));
+}
+
 constexpr size_t kStepRingLimit = 64 * 1024;
 
 static size_t step_ring_bytes(const DevNet& n) { return static_cast<size_t>(n.D) * 2 * n.G * sizeof(uint32_t); }

@@ -7,7 +7,7 @@
 //
 // Inside a part the records are laid out in rows of 64 where lane l of every
 // row holds a synapse of post-neuron l ("lane-owned" rows): row r carries the
-// r-th synapse of each post, or a zero-weight filler where that post has no
+// r-th synapse of each post, or a filler (weight -0.0) where that post has no
 // more.  A lane then sums its post's input in a register, with no atomic
 // operation.  Rows stop at R, chosen per part to balance filler slots
 // against the synapses of the few posts with more than R; those overflow
@@ -65,6 +65,13 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
     for (int64_t k = 0; k < nnz; ++k) order[fill[post[k]]++] = k;
   }
   L.recs.reserve(static_cast<size_t>(nnz) + static_cast<size_t>(nnz) / 4 + 128 * static_cast<size_t>(G));
+  L.src.reserve(L.recs.capacity());
+  // a synapse's weight, with -0 stored as +0 (-0 marks fillers)
+  auto weight = [&](int64_t k) { return w[k] == 0.f ? 0.f : w[k]; };
+  auto filler = [&](uint32_t delay, uint32_t lane) {
+    L.recs.push_back(Rec{-0.f, pack_meta(0u, delay, lane)});
+    L.src.push_back(-1);
+  };
   L.gptr.assign(static_cast<size_t>(G) + 1, 0);
   L.gsplit.assign(static_cast<size_t>(G), 0);
   std::vector<std::vector<int64_t>> lists(kGroup);
@@ -84,16 +91,17 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
         }
         deg[l] = static_cast<int64_t>(lists[l].size());
       }
-      // a filler names neuron 0 with a delay of this part and weight 0
+      // a filler names neuron 0 with a delay of this part and weight -0
       const uint32_t fill_delay = part == 0 ? 2u : 1u;
       const int64_t R = lane_rows(deg);
       for (int64_t r = 0; r < R; ++r) {
         for (int l = 0; l < kGroup; ++l) {
           if (deg[l] > r) {
             const int64_t k = lists[l][r];
-            L.recs.push_back(Rec{w[k], pack_meta(static_cast<uint32_t>(pre[k]), delay[k], static_cast<uint32_t>(l))});
+            L.recs.push_back(Rec{weight(k), pack_meta(static_cast<uint32_t>(pre[k]), delay[k], static_cast<uint32_t>(l))});
+            L.src.push_back(static_cast<int32_t>(k));
           } else {
-            L.recs.push_back(Rec{0.f, pack_meta(0u, fill_delay, static_cast<uint32_t>(l))});
+            filler(fill_delay, static_cast<uint32_t>(l));
           }
         }
       }
@@ -105,12 +113,12 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
         for (int l = 0; l < kGroup; ++l) {
           if (deg[l] <= r) continue;
           const int64_t k = lists[l][r];
-          L.recs.push_back(Rec{w[k], pack_meta(static_cast<uint32_t>(pre[k]), delay[k], static_cast<uint32_t>(l))});
+          L.recs.push_back(Rec{weight(k), pack_meta(static_cast<uint32_t>(pre[k]), delay[k], static_cast<uint32_t>(l))});
+          L.src.push_back(static_cast<int32_t>(k));
           ++count;
         }
       }
-      for (; count % kGroup != 0; ++count)
-        L.recs.push_back(Rec{0.f, pack_meta(0u, fill_delay, static_cast<uint32_t>(count % kGroup))});
+      for (; count % kGroup != 0; ++count) filler(fill_delay, static_cast<uint32_t>(count % kGroup));
     }
     L.max_group_records = std::max<int32_t>(L.max_group_records, static_cast<int32_t>(L.recs.size() - L.gptr[g]));
   }

@@ -34,12 +34,16 @@ constexpr int kChunk = 256;
 // group, delay >= 2 part then delay-1 part, each part in lane-owned rows of
 // 64 (lane l: a synapse of post l or a zero-weight filler) followed by the
 // overflow of high in-degree posts; every section a multiple of 64 records.
+// Fillers carry the weight -0.0f (input weights of zero are stored as +0.0f),
+// which adds nothing and marks them for the plasticity kernel.
 struct HostLayout {
   std::vector<Rec> recs;
+  std::vector<int32_t> src;     // input index of every record, -1 for fillers
   std::vector<int32_t> gptr;    // [G + 1] record offset of every group
   std::vector<int32_t> gsplit;  // [G] first delay-1 record of every group
   int32_t max_group_records = 0;
 };
+
 
 // Partition of the groups into P contiguous slices for the persistent kernel.
 struct SlicePlan {
@@ -94,6 +98,17 @@ struct SimArgs {
   int32_t P;
   int32_t ng_max;           // most groups in one slice
   int64_t max_recs;         // most records in one slice
+};
+
+// Plasticity (sn_set_stdp): the rule of the header, applied to the pull
+// records after the update of step t by k_stdp.
+struct StdpArgs {
+  DevNet n;
+  Rec* recs;        // the records of n, written in place
+  int32_t window;   // W, 1..16
+  float ltp[16];    // ltp[lag], lag = t - arrival < W
+  float ltd[16];    // ltd[lag - 1], lag = t - post spike in 1..W
+  float w_min, w_max;
 };
 
 // Dense delay-1 weights for the matrix-core path, bfloat16, tiled for
@@ -190,6 +205,8 @@ int batch_blocks_per_cu(size_t lds);
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
+hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
+hipError_t prepare_stdp_kernel();
 hipError_t prepare_step_kernel(const DevNet& n);
 hipError_t launch_dense_step(const DenseArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_push(const PushArgs& a, int32_t t0, int32_t steps, hipStream_t s);

@@ -92,6 +92,7 @@ class Network:
                                          ctypes.byref(self._alloc.struct) if self._alloc else None,
                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self.h = handle
+        self.nnz = 0
 
     @classmethod
     def from_workload(cls, net, **kw) -> "Network":
@@ -113,11 +114,13 @@ class Network:
         delay = np.ascontiguousarray(delay, np.uint8)
         check(self.lib.sn_load_weights_delays(self.h, pre.shape[0], pre.ctypes.data, post.ctypes.data,
                                               w.ctypes.data, delay.ctypes.data))
+        self.nnz = int(pre.shape[0])
 
     def load_dense_weights(self, W, delay: int = 1):
         W = np.ascontiguousarray(W, np.float32)
         assert W.shape == (self.n, self.n)
         check(self.lib.sn_load_dense_weights(self.h, W.ctypes.data, int(delay)))
+        self.nnz = int(np.count_nonzero(W))
 
     def set_input_spikes(self, t0: int, spikes: np.ndarray):
         """spikes: uint8 0/1 [B][steps][N] or packed uint32 [B][steps][ceil(N/32)]."""
@@ -139,6 +142,25 @@ class Network:
 
     def set_slices(self, slices: int):
         check(self.lib.sn_set_slices(self.h, int(slices)))
+
+    def set_stdp(self, window: int, ltp, ltd, w_min: float, w_max: float):
+        """Plasticity on (sn_set_stdp): ltp / ltd hold ``window`` amplitudes."""
+        d = _lib.SnStdpDesc()
+        d.window = int(window)
+        for k in range(int(window)):
+            d.ltp[k] = float(ltp[k])
+            d.ltd[k] = float(ltd[k])
+        d.w_min, d.w_max = float(w_min), float(w_max)
+        check(self.lib.sn_set_stdp(self.h, ctypes.byref(d)))
+
+    def stdp_off(self):
+        check(self.lib.sn_set_stdp(self.h, None))
+
+    def read_weights(self) -> np.ndarray:
+        """Current weights in the order of the loaded synapse list."""
+        w = np.zeros(self.nnz, np.float32)
+        check(self.lib.sn_read_weights(self.h, w.ctypes.data_as(ctypes.c_void_p)))
+        return w
 
     def autotune(self, steps: int = 64):
         """Times every strategy that can run this network over `steps` steps

@@ -1,0 +1,95 @@
+"""Plasticity on the GPU (sn_set_stdp, per-step path) against the oracle's
+rule: rasters, final state and final weights bit for bit."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from paper_2305_02510_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+LTP = [16 / 64, 8 / 64, 4 / 64, 2 / 64, 1 / 64, 1 / 64, 1 / 64, 1 / 64]
+LTD = [12 / 64, 6 / 64, 3 / 64, 2 / 64, 1 / 64, 1 / 64, 1 / 64, 1 / 64]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_02510_amd import Network
+    return Network
+
+
+def run_stdp(Network, net, window, w_min, w_max, chunks):
+    g = Network.from_workload(net)
+    g.set_stdp(window, LTP, LTD, w_min, w_max)
+    for c in chunks:
+        g.run(c)
+    spikes = g.read_raster(0, net.steps)[0]
+    V, ref = g.read_state()
+    w = g.read_weights()
+    path = g.progress[1]
+    g.close()
+    return spikes, V[0], ref[0], w, path
+
+
+def check(net, res, spikes, V, ref, w, what):
+    assert res.exact, f"{what}: input violates the exactness premise"
+    if not np.array_equal(spikes, res.spikes):
+        t, j = np.argwhere(spikes != res.spikes)[0]
+        raise AssertionError(f"{what}: raster differs first at step {t} neuron {j}")
+    assert np.array_equal(V.astype(np.float64), res.V), f"{what}: V differs"
+    assert np.array_equal(ref.astype(np.int32), res.ref), f"{what}: refractory counters differ"
+    bad = np.flatnonzero(w.astype(np.float64) != res.weight)
+    assert bad.size == 0, f"{what}: {bad.size} weights differ, first synapse {bad[:1]}"
+
+
+@pytest.mark.parametrize("seed,n,window,chunks", [(1, 60, 5, [20, 100]), (2, 250, 8, [40, 80]),
+                                                   (3, 130, 1, [120]), (4, 300, 3, [7, 33, 80])])
+def test_stdp_small_nets(gpu, oracle, seed, n, window, chunks):
+    net = wl.random_small(600 + seed, n=n, p=0.08, max_delay=4, steps=sum(chunks), drive_p=0.15)
+    res = oracle.stdp(net, window, LTP, LTD, -1.0, 1.5)
+    assert (res.weight != net.weight).any(), "the rule changed no weight: a weak test"
+    out = run_stdp(gpu, net, window, -1.0, 1.5, chunks)
+    assert out[4] == "step"
+    check(net, res, *out[:4], f"seed={seed} n={n} window={window}")
+
+
+def test_stdp_larger_net(gpu, oracle):
+    """N = 3000, p = 0.02 (about 180k synapses), delays 1..16, 150 steps."""
+    net = wl.large_sparse(21, n=3000, p=0.02, steps=150)
+    res = oracle.stdp(net, 8, LTP, LTD, -0.5, 1.0)
+    out = run_stdp(gpu, net, 8, -0.5, 1.0, [50, 100])
+    check(net, res, *out[:4], "large")
+
+
+def test_stdp_rules_of_use(gpu, oracle):
+    from paper_2305_02510_amd._lib import SnError
+    net = wl.random_small(610, n=80, p=0.1, max_delay=3, steps=40)
+    g = gpu.from_workload(net)
+    g.set_stdp(4, LTP, LTD, -1.0, 1.5)
+    g.set_path("persist")
+    with pytest.raises(SnError):
+        g.run(10)                       # plasticity runs on the per-step path only
+    with pytest.raises(SnError):
+        g.autotune(8)                   # timing would change the weights
+    g.set_path("auto")
+    g.run(40)
+    g.stdp_off()
+    g.set_path("push")
+    with pytest.raises(SnError):
+        g.run(5)                        # event-driven records hold the old weights
+    g.close()
+    two = wl.random_small(611, n=40, p=0.1, max_delay=3, steps=10, trials=2)
+    g = gpu.from_workload(two)
+    with pytest.raises(SnError):
+        g.set_stdp(4, LTP, LTD, -1.0, 1.5)  # one trial only
+    g.close()
+    # weights read back without plasticity are the loaded ones
+    g = gpu.from_workload(net)
+    assert np.array_equal(g.read_weights(), net.weight.astype(np.float32))
+    g.close()
