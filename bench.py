@@ -16,6 +16,10 @@ device memory.  Workloads:
                           batched persistent launch vs one run per net
   large_sparse_stdp       large_sparse with the plasticity rule on (window 8,
                           per-step path): simulation + weight updates
+  paper_scale_dense       the paper's largest run: N = 100,000 all-to-all
+                          dense delay-1 weights (int8 numerators, 10 GB in
+                          HBM), one trial, T = 1000; each step reads only the
+                          rows of the neurons that spiked
   bptt                    surrogate-gradient training step of a recurrent
                           layer: N = 2048, 256 inputs, 128 trials, T = 200
                           (forward + backward through time), FP32 matrix cores
@@ -196,6 +200,74 @@ def bench_single(args, net, kind):
     return out
 
 
+def bench_rows(args):
+    """The paper's largest run (N = 100,000 all-to-all, one trial, T = 1000)
+    on the dense-rows path: reset + run(T) per benchmark step.  The CPU leg
+    runs the oracle on sampled neurons, each driven by the GPU raster, and
+    checks their spikes and final state."""
+    from paper_2305_02510_amd import Network
+    from paper_2305_02510_amd import workloads as wl
+    net = wl.paper_scale_dense()
+    T, N = net.steps, net.n
+    posts = np.sort(np.random.default_rng(5).choice(N, args.cpu_posts, replace=False)).astype(np.int32)
+    t_setup = time.perf_counter()
+    g, cols = Network.from_rows_workload(net, posts=posts, workers=16)  # draw + upload 10 GB: setup
+    g.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    tuned = None
+    if args.path == "autotune":
+        tuned = g.autotune(min(T, 128))
+    else:
+        g.set_path(args.path)
+
+    def one_run():
+        g.reset_state()
+        g.run(T)
+
+    ms, wall = timed(one_run, g.stream, args.warmup, args.steps)
+    raster = g.read_raster(0, T)
+    V, ref = g.read_state()
+    path = g.progress[1]
+    out_degree = g.out_degree
+    g.close()
+    ev = events_of(raster, out_degree)
+    sec_per_tstep = ms / 1e3 / T
+    # algorithmic bytes: the int8 row of every neuron that spiked the step
+    # before (N bytes), plus the neuron state read and written
+    row_bytes = float(raster[0, :-1].sum()) * N / T
+    bytes_step = row_bytes + 10.0 * N
+    achieved = bytes_step / sec_per_tstep / 1e9
+    out = {"value": ev / (ms / 1e3), "ms_per_step": ms, "wall": wall, "events_per_run": ev,
+           "mean_firing_rate": float(raster.mean()), "path": path, "autotuned": tuned, "setup_s": setup_s,
+           "neuron_updates_per_s": N * T / (ms / 1e3), "dtype": "i8 -> i32",
+           "config": {"workload": f"{net.name}: N={N} all-to-all dense delay-1 weights (int8 k/64, "
+                                  f"{int(out_degree.sum())} non-zero), trials=1, T={T}",
+                      "time_steps_per_run": T, "trials": 1}}
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_dense_rows",
+        "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3),
+        "spiking_rows_per_time_step": round(float(raster[0, :-1].sum()) / T, 1)}
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.default()
+        c0 = time.perf_counter()
+        res = orc.run_columns(net, posts, cols.astype(np.float64) / 64.0, raster)
+        csec = time.perf_counter() - c0
+        counts = raster.sum(axis=(0, 1), dtype=np.int64)
+        ev_cpu = int(((cols != 0) @ counts).sum())
+        out["cpu_baseline"] = {
+            "value": round(ev_cpu / csec, 1), "unit": "synaptic events/s", "cores": cpu_threads_used(),
+            "kind": "oracle",
+            "sample": f"{len(posts)} of {N} neurons, each over all {T} steps driven by the GPU raster "
+                      f"(the oracle's column-wise dense update): {csec:.2f} s single-threaded"}
+        out["parity_bit_exact"] = bool(
+            np.array_equal(raster[:, :, posts], res.spikes) and np.array_equal(V[:, posts].astype(np.float64), res.V)
+            and np.array_equal(ref[:, posts].astype(np.int32), res.ref))
+        out["parity_sample"] = f"{len(posts)} sampled neurons, all steps"
+    return out
+
+
 def bench_batch(args):
     """512 uneven nets: one batched persistent launch per benchmark step,
     compared with one run per net (each net on its own best single-net path,
@@ -303,7 +375,7 @@ def bench_bptt(args):
                            f"{prob.checkpoint} steps, dense delay-1 weights", "trials": B, "time_steps_per_run": T}}
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": None,
-                       "kernel": "k_bptt_forward + k_bptt_backward + k_bptt_wgrad (whole step)",
+                       "kernel": "k_bptt_part + k_bptt_fwd_epi + k_bptt_bwd_epi + k_bptt_wgrad (whole step)",
                        "flops_per_step": flops}
     if not args.no_cpu_baseline:
         import oracle
@@ -338,10 +410,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_sparse",
                     choices=["large_sparse", "single_lif", "large_sparse_low", "dense_trials", "uneven_batch", "bptt",
-                             "large_sparse_stdp"])
+                             "large_sparse_stdp", "paper_scale_dense"])
     ap.add_argument("--path", default="autotune",
                     help="autotune (sn_autotune picks), auto (built-in heuristic) or a path name")
     ap.add_argument("--cpu-trials", type=int, default=2)
+    ap.add_argument("--cpu-posts", type=int, default=16,
+                    help="paper_scale_dense: neurons the oracle recomputes for the CPU leg and the parity check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB (read 256 MiB, write 256 MiB) and exit; "
@@ -384,6 +458,9 @@ def main():
         desc = (f"uneven_batch: {r['nets']} independent nets, N log-uniform 50..5000 (total {r['total_neurons']}), "
                 f"p 0.005..0.2 (total {r['total_synapses']} synapses), D 1..16, T=500")
         cfg = {"workload": desc, "nets": r["nets"], "time_steps_per_run": 500}
+    elif args.workload == "paper_scale_dense":
+        r = bench_rows(args)
+        cfg = r["config"]
     else:
         net = wl.by_name("large_sparse" if args.workload == "large_sparse_stdp" else args.workload)
         kind = {"dense_trials": "dense", "large_sparse_stdp": "stdp"}.get(args.workload, "sparse")

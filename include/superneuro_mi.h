@@ -73,7 +73,9 @@ enum {
   SN_PATH_DENSE = 4,    /* dense weights on matrix cores (needs sn_load_dense_weights): one cooperative
                            launch with the weights resident on chip when they fit, else as SN_PATH_DENSE_STEP */
   SN_PATH_PUSH = 5,     /* event-driven: only synapses of spiking neurons are touched (low firing rates) */
-  SN_PATH_DENSE_STEP = 6  /* dense weights on matrix cores, one launch per step */
+  SN_PATH_DENSE_STEP = 6, /* dense weights on matrix cores, one launch per step */
+  SN_PATH_DENSE_ROWS = 10 /* dense int8 rows (needs sn_load_dense_rows_i8): one launch per step reading
+                             only the rows of the neurons that spiked at the step before */
 };
 
 /* Device-memory allocator.  alloc returns device memory of at least `bytes`
@@ -138,6 +140,29 @@ sn_status sn_load_weights_delays(sn_net* net, int64_t nnz, const int32_t* pre, c
  * and also loads the nonzeros as a sparse list for the other paths.
  * Errors: SN_EINVAL, SN_ERANGE (delay), SN_EINEXACT, SN_ENOMEM, SN_EDEVICE. */
 sn_status sn_load_dense_weights(sn_net* net, const float* W, int32_t delay);
+
+/* Dense delay-1 weights of a large net (the paper's largest run is 100,000
+ * neurons all-to-all, §4), given block by block as int8 numerators:
+ * W[i][j] = k[i][j] * 2^-e (row = pre-neuron, column = post-neuron, §2.1).
+ * `k` is host memory holding rows row0 .. row0+n_rows-1, [n_rows][N]
+ * row-major, read during the call only (the copy is complete on return).
+ * The first call after creation or after another sn_load_* allocates N x Npad
+ * bytes of device memory (Npad = N rounded up to a multiple of 64), zeroed,
+ * and drops earlier synapses or dense weights; rows never given stay zero.
+ * Every call on the same weights must pass the same e.  A later
+ * sn_load_weights_delays or sn_load_dense_weights frees the rows.  Either
+ * change of weights returns a path set for the other kind to SN_PATH_AUTO.
+ * The net then runs on SN_PATH_DENSE_ROWS (chosen by SN_PATH_AUTO; other
+ * paths return SN_ESTATE): each step reads only the rows of the neurons that
+ * spiked at the step before, (spikes) x N bytes per trial.  Integer sums of
+ * at most 131,072 numerators are exact, and so is their scaling by 2^-e; the
+ * results are then exact when thresholds, leaks, resets and amplitudes are
+ * multiples of 2^-max(e, 6) and every partial sum of the update stays below
+ * 2^(24 - max(e, 6)).  Plasticity and sn_read_weights do not apply.
+ * Errors: SN_EINVAL (k NULL with n_rows > 0, e differing from the first
+ * call's), SN_ERANGE (N > 131,072, rows outside [0, N), e outside [0, 24]),
+ * SN_ENOMEM, SN_EDEVICE. */
+sn_status sn_load_dense_rows_i8(sn_net* net, int32_t row0, int32_t n_rows, const int8_t* k, int32_t e);
 
 /* External spikes (§2.1, third step) for steps t0 .. t0+n_steps-1.  `bits`
  * is host memory laid out [B][n_steps][ceil(N/32)] uint32 words; bit (j % 32)

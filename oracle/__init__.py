@@ -47,6 +47,9 @@ def _bind(lib):
     lib.or_lif_stdp.restype = ctypes.c_int
     lib.or_lif_stdp.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P,
                                 _I32, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.or_lif_columns.restype = ctypes.c_int
+    lib.or_lif_columns.argtypes = [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _P,
+                                   _P, _P, _P, _P, _P, _P, ctypes.c_int]
     lib.or_lif_dense.restype = ctypes.c_int
     lib.or_lif_dense.argtypes = [_I32, _I32, _I32, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P, _P, ctypes.c_int]
@@ -100,21 +103,49 @@ class Oracle:
             raise ValueError(f"oracle rejected the input (status {rc})")
         return OracleResult(spikes, V, ref, rc == OR_OK)
 
-    def run_dense(self, net, steps: Optional[int] = None, trials=None) -> OracleResult:
-        """Simulate ``net`` through its dense weight matrix (delay 1)."""
-        assert net.dense_weight is not None
+    def run_dense(self, net, steps: Optional[int] = None, trials=None, W=None) -> OracleResult:
+        """Simulate ``net`` through its dense weight matrix (delay 1): W, or
+        ``net.dense_weight`` when W is None."""
+        if W is None:
+            W = net.dense_weight
+        assert W is not None
         T = net.steps if steps is None else int(steps)
         ext = net.ext[:, :T] if trials is None else net.ext[list(trials), :T]
         ext = np.ascontiguousarray(ext, dtype=np.uint8)
         B, N = ext.shape[0], net.n
         th, lk, rs, rf, am = self._params(net)
-        W = np.ascontiguousarray(net.dense_weight, dtype=np.float64)
+        W = np.ascontiguousarray(W, dtype=np.float64)
         spikes = np.zeros((B, T, N), np.uint8)
         V = np.zeros((B, N), np.float64)
         ref = np.zeros((B, N), np.int32)
         P = self._ptr
         rc = self.lib.or_lif_dense(N, B, T, P(th), P(lk), P(rs), P(rf), P(am), P(W),
                                    P(ext), P(spikes), P(V), P(ref), 1)
+        if rc not in (OR_OK, OR_NONEXACT):
+            raise ValueError(f"oracle rejected the input (status {rc})")
+        return OracleResult(spikes, V, ref, rc == OR_OK)
+
+
+    def run_columns(self, net, posts, wcol, history, steps: Optional[int] = None) -> OracleResult:
+        """Neurons ``posts`` of a dense delay-1 net, one at a time, driven by
+        the spike history ``history`` (uint8 [B][>= T][N]) of the whole network;
+        wcol [S][N] are the weight columns W[:, posts].  Returns spikes
+        [B][T][S] and the final V / ref [B][S] of the listed neurons."""
+        T = net.steps if steps is None else int(steps)
+        ext = np.ascontiguousarray(net.ext[:, :T], dtype=np.uint8)
+        B, N = ext.shape[0], net.n
+        posts = np.ascontiguousarray(posts, dtype=np.int32)
+        S = posts.shape[0]
+        wcol = np.ascontiguousarray(wcol, dtype=np.float64)
+        history = np.ascontiguousarray(np.asarray(history)[:, :T], dtype=np.uint8)
+        assert wcol.shape == (S, N) and history.shape == (B, T, N)
+        th, lk, rs, rf, am = self._params(net)
+        spikes = np.zeros((B, T, S), np.uint8)
+        V = np.zeros((B, S), np.float64)
+        ref = np.zeros((B, S), np.int32)
+        P = self._ptr
+        rc = self.lib.or_lif_columns(N, B, T, S, P(posts), P(th), P(lk), P(rs), P(rf), P(am), P(wcol),
+                                     P(history), P(ext), P(spikes), P(V), P(ref), 1)
         if rc not in (OR_OK, OR_NONEXACT):
             raise ValueError(f"oracle rejected the input (status {rc})")
         return OracleResult(spikes, V, ref, rc == OR_OK)

@@ -254,6 +254,60 @@ int or_lif_stdp(int32_t N, int32_t D, int32_t T,
 }
 
 /*
+ * Selected post-neurons of a dense delay-1 net, one at a time, given the
+ * spike history of the whole network: for neuron j = posts[k] the update of
+ * §2.1 over T steps, whose synaptic input at step t is the sum of W[i][j]
+ * over the neurons i with history[b][t-1][i] = 1.  wcol [S][N] holds the
+ * columns, wcol[k][i] = W[i][posts[k]]; parameter vectors and ext [B][T][N]
+ * cover all N neurons.  Outputs: spikes [B][T][S], V_out and ref_out [B][S].
+ * When `history` is the network's own raster, the outputs are that raster's
+ * columns and the final state of the listed neurons, so a large net can be
+ * checked neuron by neuron without simulating all of it.
+ */
+int or_lif_columns(int32_t N, int32_t B, int32_t T, int32_t S, const int32_t* posts,
+                   const double* theta, const double* leak, const double* reset,
+                   const int32_t* refractory, const double* amplitude,
+                   const double* wcol, const uint8_t* history, const uint8_t* ext,
+                   uint8_t* spikes, double* V_out, int32_t* ref_out, int check_exact) {
+    if (N < 1 || B < 1 || T < 0 || S < 0) return OR_EINVAL;
+    for (int32_t k = 0; k < S; ++k)
+        if (posts[k] < 0 || posts[k] >= N) return OR_EINVAL;
+    int exact = 1;
+    if (check_exact && !check_params(N, theta, leak, reset, refractory, amplitude)) exact = 0;
+    for (int32_t k = 0; k < S; ++k) {
+        const int32_t j = posts[k];
+        const double* w = wcol + (size_t)k * N;
+        double in_abs = 0.0;
+        for (int32_t i = 0; i < N; ++i) {
+            if (!isfinite(w[i])) return OR_EINVAL;
+            if (check_exact && w[i] != 0.0 && !on_grid(w[i])) exact = 0;
+            in_abs += fabs(w[i]);
+        }
+        for (int32_t b = 0; b < B; ++b) {
+            const uint8_t* hb = history + (size_t)b * T * N;
+            const uint8_t* xb = ext + (size_t)b * T * N;
+            double V = reset[j];
+            int32_t ref = 0;
+            for (int32_t t = 0; t < T; ++t) {
+                double U = apply_leak(V, reset[j], leak[j]);
+                if (check_exact && !(fabs(U) + in_abs + fabs(amplitude[j]) < EXACT_LIMIT)) exact = 0;
+                if (t > 0) {
+                    const uint8_t* sp = hb + (size_t)(t - 1) * N;
+                    for (int32_t i = 0; i < N; ++i)
+                        if (sp[i]) U += w[i];
+                }
+                if (xb[(size_t)t * N + j]) U += amplitude[j];
+                spikes[((size_t)b * T + t) * S + k] =
+                    (uint8_t)fire_and_reset(U, theta[j], reset[j], refractory[j], &V, &ref);
+            }
+            V_out[(size_t)b * S + k] = V;
+            ref_out[(size_t)b * S + k] = ref;
+        }
+    }
+    return exact ? OR_OK : OR_NONEXACT;
+}
+
+/*
  * Dense weight matrix W [N][N] (row = pre, column = post, §2.1), every synapse
  * of delay 1: the literal matrix form "spike vector of the previous step times
  * the weight matrix".  Same state layout as or_lif_sparse.

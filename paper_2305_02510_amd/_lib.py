@@ -11,12 +11,14 @@ SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ESTATE, SN_ERANGE, SN_EINEXACT = 0, 
 STATUS_NAMES = {0: "SN_OK", -1: "SN_EINVAL", -2: "SN_ENOMEM", -3: "SN_EDEVICE", -4: "SN_ESTATE",
                 -5: "SN_ERANGE", -6: "SN_EINEXACT"}
 PATH_AUTO, PATH_SMALL, PATH_STEP, PATH_PERSIST, PATH_DENSE, PATH_PUSH, PATH_DENSE_STEP = 0, 1, 2, 3, 4, 5, 6
+PATH_DENSE_ROWS = 10
 PATH_NAMES = {0: "auto", 1: "small", 2: "step", 3: "persist", 4: "dense", 5: "push", 6: "dense_step",
-              7: "batch", 8: "dense_persist", 9: "dense_persist_i8"}
+              7: "batch", 8: "dense_persist", 9: "dense_persist_i8", 10: "dense_rows"}
 
 # Every symbol the header declares.
 EXPORTS = [
-    "sn_create_network", "sn_load_weights_delays", "sn_load_dense_weights", "sn_set_input_spikes",
+    "sn_create_network", "sn_load_weights_delays", "sn_load_dense_weights", "sn_load_dense_rows_i8",
+    "sn_set_input_spikes",
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_autotune", "sn_get_progress", "sn_destroy_network",
     "sn_last_error", "sn_set_stdp", "sn_read_weights",
@@ -71,6 +73,7 @@ def load():
         "sn_create_network": [ctypes.POINTER(SnNetDesc), ctypes.POINTER(SnAllocator), P, ctypes.POINTER(P)],
         "sn_load_weights_delays": [P, I64, P, P, P, P],
         "sn_load_dense_weights": [P, P, I32],
+        "sn_load_dense_rows_i8": [P, I32, I32, P, I32],
         "sn_set_input_spikes": [P, I32, I32, P],
         "sn_set_input_spikes_device": [P, I32, I32, P],
         "sn_run": [P, I32],

@@ -72,11 +72,15 @@ struct sn_net {
   float scale8 = 0.f;
   int32_t kpad = 0;
   bool dense_loaded = false;
+  // dense int8 rows (sn_load_dense_rows_i8): [N][Npad] numerators, scale 2^-rows_e
+  void* rows8 = nullptr;
+  int32_t rows_e = -1;
+  bool rows_loaded = false;
   // cached graph of per-step launches
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   int32_t graph_path = -1, graph_t0 = -1, graph_steps = -1, graph_stdp = -1;
-  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  const void* graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t slices_req = 0;
   // plasticity (sn_set_stdp): on, its arguments, a generation for the graph
   // cache, and whether the event-driven records still hold the loaded weights
@@ -244,6 +248,9 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
       if (path == SN_PATH_DENSE) {
         DenseArgs a{n->d, static_cast<const uint16_t*>(n->wt), n->kpad, nullptr, 0.f};
         e = launch_dense_step(a, t0 + k, s);
+      } else if (path == SN_PATH_DENSE_ROWS) {
+        RowsArgs a{n->d, static_cast<const int8_t*>(n->rows8), n->d.Npad, std::ldexp(1.f, -n->rows_e)};
+        e = launch_dense_rows(a, t0 + k, s);
       } else {
         e = launch_step(n->d, t0 + k, s);
         if (e == hipSuccess && n->stdp_on) {
@@ -260,10 +267,10 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
     SN_HIP(n, launch_all(n->stream));
     return SN_OK;
   }
-  const void* key[4] = {n->d.raster, n->d.ext, n->d.recs, n->wt};
+  const void* key[5] = {n->d.raster, n->d.ext, n->d.recs, n->wt, n->rows8};
   const int32_t stdp_key = n->stdp_on ? n->stdp_gen : 0;
   const bool hit = n->graph && n->graph_path == path && n->graph_t0 == t0 && n->graph_steps == steps &&
-                   n->graph_stdp == stdp_key && std::equal(key, key + 4, n->graph_key);
+                   n->graph_stdp == stdp_key && std::equal(key, key + 5, n->graph_key);
   if (!hit) {
     if (n->graph) {
       SN_HIP(n, hipGraphExecDestroy(n->graph));
@@ -283,7 +290,7 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
     n->graph_t0 = t0;
     n->graph_steps = steps;
     n->graph_stdp = stdp_key;
-    std::copy(key, key + 4, n->graph_key);
+    std::copy(key, key + 5, n->graph_key);
   }
   SN_HIP(n, hipGraphLaunch(n->graph, n->stream));
   return SN_OK;
@@ -743,6 +750,11 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   }
   n->d.nnz = nnz;
   n->synapses_loaded = true;
+  dev_free(n, n->rows8);
+  n->rows8 = nullptr;
+  n->rows_loaded = false;
+  n->rows_e = -1;
+  if (n->path == SN_PATH_DENSE_ROWS) n->path = SN_PATH_AUTO;  // chosen for the rows, which are gone
   dev_free(n, n->wt);
   n->wt = nullptr;
   dev_free(n, n->wt8);
@@ -825,6 +837,52 @@ sn_status sn_load_dense_weights(sn_net* n, const float* W, int32_t delay) {
   return SN_OK;
 }
 
+sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const int8_t* k, int32_t e) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  const int32_t N = n->d.N;
+  if (N > kRowsMaxNeurons) return fail(SN_ERANGE, "dense rows support up to %d neurons (got %d)", kRowsMaxNeurons, N);
+  if (e < 0 || e > 24) return fail(SN_ERANGE, "exponent %d outside [0, 24]", e);
+  if (row0 < 0 || n_rows < 0 || static_cast<int64_t>(row0) + n_rows > N)
+    return fail(SN_ERANGE, "rows %d .. %lld outside [0, %d)", row0, static_cast<long long>(row0) + n_rows - 1, N);
+  if (n_rows > 0 && !k) return fail(SN_EINVAL, "k must not be NULL");
+  if (n->rows_loaded && e != n->rows_e)
+    return fail(SN_EINVAL, "exponent %d differs from the %d of the rows already loaded", e, n->rows_e);
+  if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
+  const size_t pitch = static_cast<size_t>(n->d.Npad);
+  if (!n->rows_loaded) {
+    // queued work may still read the buffers dropped here
+    SN_HIP(n, hipStreamSynchronize(n->stream));
+    void* r = dev_alloc(n, static_cast<size_t>(N) * pitch);
+    if (!r) return fail(SN_ENOMEM, "cannot allocate %zu bytes of dense rows", static_cast<size_t>(N) * pitch);
+    for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr}) {
+      dev_free(n, *p);
+      *p = nullptr;
+    }
+    n->d.recs = nullptr;
+    n->d.gptr = nullptr;
+    n->d.gsplit = nullptr;
+    n->d.nnz = 0;
+    n->small.ok = n->persist.ok = false;
+    n->synapses_loaded = n->dense_loaded = false;
+    n->stdp_on = false;
+    n->layout = HostLayout{};
+    n->nnz_loaded = 0;
+    n->rows8 = r;
+    n->rows_e = e;
+    n->rows_loaded = true;
+    n->path = SN_PATH_AUTO;  // a path chosen for the dropped weights does not apply
+    SN_HIP(n, hipMemsetAsync(r, 0, static_cast<size_t>(N) * pitch, n->stream));
+  }
+  if (n_rows > 0) {
+    SN_HIP(n, hipMemcpy2DAsync(static_cast<int8_t*>(n->rows8) + static_cast<size_t>(row0) * pitch, pitch, k,
+                               static_cast<size_t>(N), static_cast<size_t>(N), static_cast<size_t>(n_rows),
+                               hipMemcpyHostToDevice, n->stream));
+  }
+  SN_HIP(n, hipStreamSynchronize(n->stream));  // the caller may reuse k on return
+  return SN_OK;
+}
+
 sn_status sn_set_input_spikes(sn_net* n, int32_t t0, int32_t n_steps, const uint32_t* bits) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
@@ -874,7 +932,8 @@ sn_status sn_set_input_spikes_device(sn_net* n, int32_t t0, int32_t n_steps, con
 sn_status sn_set_path(sn_net* n, int32_t path) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
-  if (path < SN_PATH_AUTO || path > SN_PATH_DENSE_STEP) return fail(SN_ERANGE, "unknown path %d", path);
+  if ((path < SN_PATH_AUTO || path > SN_PATH_DENSE_STEP) && path != SN_PATH_DENSE_ROWS)
+    return fail(SN_ERANGE, "unknown path %d", path);
   n->path = path;
   return SN_OK;
 }
@@ -889,7 +948,7 @@ sn_status sn_get_progress(sn_net* n, int32_t* t, int32_t* path) {
 sn_status sn_run(sn_net* n, int32_t n_steps) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
-  if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_run");
+  if (!n->synapses_loaded && !n->rows_loaded) return fail(SN_ESTATE, "load synapses before sn_run");
   if (n_steps < 0) return fail(SN_ERANGE, "n_steps must be >= 0");
   if (static_cast<int64_t>(n->t) + n_steps > INT32_MAX) return fail(SN_ERANGE, "step counter overflows");
   if (n_steps == 0) return SN_OK;
@@ -905,10 +964,14 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
   }
   if (path == SN_PATH_PUSH && n->push_stale)
     return fail(SN_ESTATE, "plasticity changed the weights: reload them before the event-driven path");
+  if (n->rows_loaded != (path == SN_PATH_DENSE_ROWS) && !(n->rows_loaded && path == SN_PATH_AUTO))
+    return fail(SN_ESTATE, n->rows_loaded ? "dense rows run only on SN_PATH_DENSE_ROWS"
+                                          : "SN_PATH_DENSE_ROWS needs sn_load_dense_rows_i8");
   if (path == SN_PATH_AUTO) {
     // one workgroup when its records and spike ring fit in LDS, otherwise one
     // launch per step
-    if (n->dense_loaded) path = SN_PATH_DENSE;
+    if (n->rows_loaded) path = SN_PATH_DENSE_ROWS;
+    else if (n->dense_loaded) path = SN_PATH_DENSE;
     else if (n->small.ok && n->small.host.recs_lds && n->small.host.ring_lds) path = SN_PATH_SMALL;
     else if (n->persist.ok && n->persist.host.P > 1 && n->persist.host.recs_lds && n->persist.host.ring_lds)
       path = SN_PATH_PERSIST;
@@ -934,6 +997,10 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
       break;
     case SN_PATH_PUSH:
       st = run_push(n, n->t, n_steps);
+      if (st != SN_OK) return st;
+      break;
+    case SN_PATH_DENSE_ROWS:
+      st = run_per_step(n, SN_PATH_DENSE_ROWS, n->t, n_steps);
       if (st != SN_OK) return st;
       break;
     case SN_PATH_DENSE:
@@ -1019,6 +1086,7 @@ sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
     n->stdp_on = false;
     return SN_OK;
   }
+  if (n->rows_loaded) return fail(SN_ESTATE, "plasticity applies to synapse lists, not dense rows");
   if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_set_stdp");
   if (n->dense_loaded) return fail(SN_ESTATE, "plasticity applies to synapse lists, not dense weights");
   if (n->d.B != 1) return fail(SN_ERANGE, "plasticity needs one trial (got %d)", n->d.B);
@@ -1047,6 +1115,7 @@ sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
 sn_status sn_read_weights(sn_net* n, float* w) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
+  if (n->rows_loaded) return fail(SN_ESTATE, "weights loaded as dense rows are not read back");
   if (!n->synapses_loaded) return fail(SN_ESTATE, "no synapses loaded");
   if (n->nnz_loaded > 0 && !w) return fail(SN_EINVAL, "w must not be NULL");
   std::vector<Rec> recs(n->layout.recs.size());
@@ -1061,7 +1130,7 @@ sn_status sn_read_weights(sn_net* n, float* w) {
 sn_status sn_autotune(sn_net* n, int32_t steps, int32_t* path_out, int32_t* slices_out) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
-  if (!n->synapses_loaded) return fail(SN_ESTATE, "load synapses before sn_autotune");
+  if (!n->synapses_loaded && !n->rows_loaded) return fail(SN_ESTATE, "load synapses before sn_autotune");
   if (steps < 1 || steps > 4096) return fail(SN_ERANGE, "steps %d outside [1, 4096]", steps);
   if (n->stdp_on) return fail(SN_ESTATE, "plasticity would change the weights while timing: turn it off first");
   if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
@@ -1069,7 +1138,9 @@ sn_status sn_autotune(sn_net* n, int32_t steps, int32_t* path_out, int32_t* slic
     int32_t path, slices;
   };
   std::vector<Cand> cands;
-  if (n->dense_loaded) {
+  if (n->rows_loaded) {
+    cands = {{SN_PATH_DENSE_ROWS, 0}};
+  } else if (n->dense_loaded) {
     cands = {{SN_PATH_DENSE, 0}, {SN_PATH_DENSE_STEP, 0}};
   } else {
     if (n->small.ok) cands.push_back({SN_PATH_SMALL, 0});
@@ -1096,7 +1167,7 @@ sn_status sn_autotune(sn_net* n, int32_t steps, int32_t* path_out, int32_t* slic
   float best_ms = 0.f;
   for (const Cand& c : cands) {
     n->path = c.path;
-    if (c.path == SN_PATH_PERSIST || n->slices_req != c.slices) {
+    if (n->synapses_loaded && (c.path == SN_PATH_PERSIST || n->slices_req != c.slices)) {
       n->slices_req = c.slices;
       st = upload_plan(n, n->persist, plan_persist(n->d, n->layout, c.slices));
       if (st != SN_OK) break;
@@ -1125,7 +1196,7 @@ sn_status sn_autotune(sn_net* n, int32_t steps, int32_t* path_out, int32_t* slic
   if (st != SN_OK) return st;
   if (best.path == SN_PATH_AUTO) return fail(SN_ERANGE, "no strategy could run the network");
   n->path = best.path;
-  if (n->slices_req != best.slices) {
+  if (n->synapses_loaded && n->slices_req != best.slices) {
     n->slices_req = best.slices;
     st = upload_plan(n, n->persist, plan_persist(n->d, n->layout, best.slices));
     if (st != SN_OK) return st;
@@ -1158,6 +1229,7 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->persist.wg);
   dev_free(n, n->wt);
   dev_free(n, n->wt8);
+  dev_free(n, n->rows8);
   dev_free(n, n->orecs);
   dev_free(n, n->optr);
   dev_free(n, n->push_wg);

@@ -139,6 +139,18 @@ void tile_dense_weights(const float* W, int32_t n, int32_t npad, int32_t kpad, u
 int32_t int8_exponent(const float* W, int64_t count);
 void tile_dense_weights_i8(const float* W, int32_t n, int32_t npad, int32_t kpad, int32_t e, int8_t* out);
 
+// Dense delay-1 weights of a large net, row-major int8 numerators:
+// W[i][j] = w8[i * pitch + j] * scale, scale = 2^-e, pitch = Npad (rows N).
+// Sums of at most kRowsMaxNeurons numerators of magnitude <= 128 stay below
+// 2^24 and convert to binary32 exactly.
+constexpr int32_t kRowsMaxNeurons = 131072;
+struct RowsArgs {
+  DevNet n;
+  const int8_t* w8;
+  int64_t pitch;
+  float scale;
+};
+
 // Event-driven ("push") delivery: out-going synapses of every neuron (CSR by
 // pre-neuron) and a ring of D + 1 accumulator rows; a spike of neuron i at t
 // adds w into row (t + d) mod (D+1) at the post-neuron.
@@ -209,6 +221,7 @@ hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
 hipError_t prepare_stdp_kernel();
 hipError_t prepare_step_kernel(const DevNet& n);
 hipError_t launch_dense_step(const DenseArgs& a, int32_t t, hipStream_t s);
+hipError_t launch_dense_rows(const RowsArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_push(const PushArgs& a, int32_t t0, int32_t steps, hipStream_t s);
 hipError_t prepare_dense_kernel(int32_t kpad);
 size_t dense_persist_lds_bytes(int32_t kpad);

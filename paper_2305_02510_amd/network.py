@@ -17,7 +17,7 @@ from ._lib import check
 
 PATHS = {"auto": _lib.PATH_AUTO, "small": _lib.PATH_SMALL, "step": _lib.PATH_STEP,
          "persist": _lib.PATH_PERSIST, "dense": _lib.PATH_DENSE, "push": _lib.PATH_PUSH,
-         "dense_step": _lib.PATH_DENSE_STEP}
+         "dense_step": _lib.PATH_DENSE_STEP, "dense_rows": _lib.PATH_DENSE_ROWS}
 
 
 class TorchAllocator:
@@ -106,6 +106,31 @@ class Network:
         g.set_input_spikes(0, net.ext)
         return g
 
+    @classmethod
+    def from_rows_workload(cls, net, posts=None, workers: int = 8, **kw):
+        """Build from a workloads.RowsNetwork: its int8 row blocks are drawn
+        in ``workers`` threads and loaded in order with sn_load_dense_rows_i8.
+        Returns (network, cols): cols is int8 [len(posts)][N] = k[:, posts]
+        when ``posts`` is given (columns for checking sampled neurons), else
+        None.  ``network.out_degree`` holds the non-zero weights of every row."""
+        from concurrent.futures import ThreadPoolExecutor
+        g = cls(net.n, net.trials, 1, net.threshold, net.leak, net.reset, net.refractory, net.amplitude, **kw)
+        posts = None if posts is None else np.asarray(posts, np.int64)
+        cols = None if posts is None else np.empty((posts.shape[0], net.n), np.int8)
+        g.out_degree = np.zeros(net.n, np.int64)
+        window = max(1, 2 * workers)
+        with ThreadPoolExecutor(max(1, workers)) as ex:
+            for w0 in range(0, net.n_blocks, window):
+                idx = range(w0, min(net.n_blocks, w0 + window))
+                for bi, k in zip(idx, ex.map(net.block, idx)):
+                    r0 = bi * net.block_rows
+                    g.load_dense_rows_i8(r0, k, net.e)
+                    g.out_degree[r0:r0 + k.shape[0]] = np.count_nonzero(k, axis=1)
+                    if cols is not None:
+                        cols[:, r0:r0 + k.shape[0]] = k[:, posts].T
+        g.set_input_spikes(0, net.ext)
+        return g, cols
+
     # -- loading -----------------------------------------------------------
     def load_weights_delays(self, pre, post, w, delay):
         pre = np.ascontiguousarray(pre, np.int32)
@@ -121,6 +146,14 @@ class Network:
         assert W.shape == (self.n, self.n)
         check(self.lib.sn_load_dense_weights(self.h, W.ctypes.data, int(delay)))
         self.nnz = int(np.count_nonzero(W))
+
+    def load_dense_rows_i8(self, row0: int, k, e: int):
+        """Rows row0 .. row0 + len(k) - 1 of dense delay-1 weights W = k * 2^-e,
+        k an int8 array [rows][N] (sn_load_dense_rows_i8)."""
+        k = np.ascontiguousarray(k, np.int8)
+        assert k.ndim == 2 and k.shape[1] == self.n
+        check(self.lib.sn_load_dense_rows_i8(self.h, int(row0), int(k.shape[0]), k.ctypes.data, int(e)))
+        self.nnz = 0
 
     def set_input_spikes(self, t0: int, spikes: np.ndarray):
         """spikes: uint8 0/1 [B][steps][N] or packed uint32 [B][steps][ceil(N/32)]."""

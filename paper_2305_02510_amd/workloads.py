@@ -308,6 +308,103 @@ def paper_table_shape(seed: int, n: int, p: float, steps: int = 1000) -> Network
                    pre, post, w, d, ext)
 
 
+ROW_BLOCK = 256  # rows of a dense-rows net drawn from one Philox stream
+
+
+def _byte_table(counts) -> np.ndarray:
+    """256-entry table mapping a uniform byte to k: value k fills counts[k]
+    consecutive entries (counts sum to 256), so P(k) = counts[k] / 256."""
+    table = np.concatenate([np.full(c, k, np.int8) for k, c in sorted(counts.items())])
+    assert table.shape == (256,)
+    return table
+
+
+@dataclasses.dataclass
+class RowsNetwork:
+    """A dense delay-1 net too large to hold its weights as one array:
+    W = k * 2^-e (row = pre, column = post) with int8 numerators drawn on
+    demand, ROW_BLOCK rows per Philox stream, so any block of rows is
+    reproducible on its own.  Pre-neuron i is inhibitory (row i <= 0) or
+    excitatory (row i >= 0); within a row every entry is an independent byte
+    mapped through the row type's table; the diagonal is zero.  ``ext`` is the
+    external spike raster, uint8 [trials][steps][n] of 0/1."""
+    name: str
+    n: int
+    trials: int
+    steps: int
+    e: int
+    seed: int
+    threshold: np.ndarray
+    leak: np.ndarray
+    reset: np.ndarray
+    refractory: np.ndarray
+    amplitude: np.ndarray
+    inhibitory: np.ndarray  # bool [n]
+    table_exc: np.ndarray   # int8 [256]
+    table_inh: np.ndarray   # int8 [256]
+    ext: np.ndarray
+
+    def block(self, bi: int) -> np.ndarray:
+        """Rows bi * ROW_BLOCK .. of k, int8 [rows][n]."""
+        r0 = bi * ROW_BLOCK
+        r1 = min(self.n, r0 + ROW_BLOCK)
+        rows = r1 - r0
+        raw = rng_for(self.seed, "w", bi).bit_generator.random_raw((rows * self.n + 7) // 8)
+        u = raw.view(np.uint8)[: rows * self.n].reshape(rows, self.n)
+        k = np.empty((rows, self.n), np.int8)
+        for r in range(rows):
+            np.take(self.table_inh if self.inhibitory[r0 + r] else self.table_exc, u[r], out=k[r])
+            k[r, r0 + r] = 0
+        return k
+
+    @property
+    def n_blocks(self) -> int:
+        return (self.n + ROW_BLOCK - 1) // ROW_BLOCK
+
+    @property
+    def block_rows(self) -> int:
+        return ROW_BLOCK
+
+    def rows(self, r0: int, r1: int) -> np.ndarray:
+        """Rows r0 .. r1 - 1 of k."""
+        out = np.empty((r1 - r0, self.n), np.int8)
+        for bi in range(r0 // ROW_BLOCK, (r1 + ROW_BLOCK - 1) // ROW_BLOCK):
+            k = self.block(bi)
+            a, b = max(r0, bi * ROW_BLOCK), min(r1, bi * ROW_BLOCK + k.shape[0])
+            out[a - r0:b - r0] = k[a - bi * ROW_BLOCK:b - bi * ROW_BLOCK]
+        return out
+
+    def dense(self) -> np.ndarray:
+        """All of W as float32 (small nets only)."""
+        return (self.rows(0, self.n).astype(np.float32) * np.float32(2.0 ** -self.e))
+
+
+def paper_scale_dense(seed: int = 6, n: int = 100_000, trials: int = 1, steps: int = 1000,
+                      exc=None, inh=None, inh_frac: float = 0.2, drive_frac: float = 1.0,
+                      drive_p: float = 0.02, leak: float = 0.25) -> RowsNetwork:
+    """The paper's largest run (§4: 100,000 neurons, all-to-all, matrix mode)
+    as a synthetic dense delay-1 net.  The paper states neither weights nor
+    steps.  Here W = k / 64 with 20% inhibitory pre-neurons and byte-table
+    distributions balanced on average (``exc``: k = 1 with probability 1/4,
+    else 0; ``inh``: k = -1), so the input of a neuron has mean about zero and
+    a spread that grows with the number of spiking neurons; every neuron is
+    driven Bernoulli(0.02) per step with amplitude 2 (as the dense-trials
+    net); threshold 1, reset 0, leak 2^-2, refractory 2; T = 1000.  At
+    N = 100,000 the rate swings between about 0.5% and 7% per step."""
+    th, lk, rs, rf, am = _params(n, 1.0, leak, 0.0, 2, 2.0)
+    inh_mask = np.zeros(n, bool)
+    inh_mask[rng_for(seed, "sel").permutation(n)[: int(round(inh_frac * n))]] = True
+    t_exc = _byte_table(exc if exc is not None else {0: 192, 1: 64})
+    t_inh = _byte_table(inh if inh is not None else {-1: 256})
+    driven = np.zeros(n, bool)
+    driven[rng_for(seed, "sel", 1).permutation(n)[: int(round(drive_frac * n))]] = True
+    ext = np.empty((trials, steps, n), np.uint8)
+    for b in range(trials):
+        ext[b] = _bernoulli_raster(rng_for(seed, "inp", b), (steps, n), drive_p) * driven
+    return RowsNetwork(f"paper_scale_dense_n{n}", n, trials, steps, 6, seed, th, lk, rs, rf, am,
+                       inh_mask, t_exc, t_inh, ext)
+
+
 def by_name(name: str, seed: Optional[int] = None) -> Network:
     table = {
         "single_lif": (single_lif, 1),

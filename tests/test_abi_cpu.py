@@ -23,7 +23,7 @@ def lib():
 def header_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sn_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sn_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_matches_binding_list():
@@ -72,6 +72,7 @@ def test_null_network_calls(lib):
     assert lib.sn_run(None, 5) == _lib.SN_EINVAL
     assert lib.sn_set_path(None, 0) == _lib.SN_EINVAL
     assert lib.sn_read_state(None, None, None) == _lib.SN_EINVAL
+    assert lib.sn_load_dense_rows_i8(None, 0, 0, None, 6) == _lib.SN_EINVAL
     lib.sn_destroy_network(None)
 
 

@@ -74,3 +74,24 @@ def test_uneven_batch_small():
         net.validate()
         assert 50 <= net.n <= 400
         assert _dyadic(net.threshold) and _dyadic(net.leak) and _dyadic(net.weight)
+
+
+def test_rows_network_blocks():
+    net = wl.paper_scale_dense(n=700, steps=5)
+    k = net.rows(0, 700)
+    assert k.dtype == np.int8 and k.shape == (700, 700)
+    assert (np.diag(k) == 0).all()
+    # any row range equals the same rows of the whole; blocks stand alone
+    np.testing.assert_array_equal(net.rows(250, 530), k[250:530])
+    np.testing.assert_array_equal(net.block(2), k[512:700])
+    np.testing.assert_array_equal(wl.paper_scale_dense(n=700, steps=5).rows(0, 700), k)
+    # row types and table values
+    assert abs(net.inhibitory.mean() - 0.2) < 0.01
+    assert (k[net.inhibitory] <= 0).all() and (k[~net.inhibitory] >= 0).all()
+    assert set(np.unique(k[~net.inhibitory]).tolist()) <= {0, 1}
+    off = ~np.eye(700, dtype=bool)
+    exc_rows = off[~net.inhibitory]
+    assert abs((k[~net.inhibitory] == 1).sum() / exc_rows.sum() - 0.25) < 0.01
+    assert (k[net.inhibitory][off[net.inhibitory]] == -1).all()
+    np.testing.assert_array_equal(net.dense(), k.astype(np.float32) / 64)
+    assert abs(wl.paper_scale_dense(n=700, steps=60).ext.mean() - 0.02) < 0.003
