@@ -214,6 +214,23 @@ def test_edge_cases(gpu, oracle):
             assert_parity(net, res, s, V, r, path)
 
 
+@pytest.fixture(scope="module")
+def max_net(oracle):
+    # the largest net the library takes: 2^20 neurons, so pre-neuron indices
+    # use every one of their 20 bits; ~4.4M synapses, delays 1..16
+    net = wl.large_sparse(31, n=1 << 20, p=4e-6, steps=30, w_k=(0, 96), name="max_neurons")
+    return net, oracle.run_sparse(net)
+
+
+@pytest.mark.parametrize("path", ["auto", "step", "push"])
+def test_max_neurons(gpu, max_net, path):
+    net, res = max_net
+    print(f"max neurons N={net.n} nnz={net.nnz} path={path}", flush=True)
+    assert (res.spikes & (1 - net.ext)).sum() > net.ext.sum(), "recurrent spikes expected"
+    s, V, r, _ = simulate(gpu, net, path)
+    assert_parity(net, res, s, V, r, path)
+
+
 def test_device_input(gpu, oracle):
     import torch
     from paper_2305_02510_amd.network import pack_bits

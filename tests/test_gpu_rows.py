@@ -95,6 +95,22 @@ def test_rows_paper_scale_sampled(gpu, oracle):
     np.testing.assert_array_equal(r[:, posts].astype(np.int32), res.ref)
 
 
+def test_rows_max_neurons_sampled(gpu, oracle):
+    # the largest net the rows path takes (131,072 neurons: one raster row is
+    # exactly the 2048 words a workgroup lists in one pass), 17 GB of weights
+    n, steps = 131072, 30
+    net = wl.paper_scale_dense(seed=29, n=n, steps=steps)
+    posts = np.array([0, 1, 64, 65535, 65536, n - 64, n - 2, n - 1], np.int32)
+    print(f"rows max neurons n={n} steps={steps}", flush=True)
+    s, V, r, used, cols = rows_run(gpu, net, posts=posts)
+    assert used == "dense_rows"
+    res = oracle.run_columns(net, posts, cols.astype(np.float64) / 64.0, s)
+    assert res.exact
+    np.testing.assert_array_equal(s[:, :, posts], res.spikes)
+    np.testing.assert_array_equal(V[:, posts].astype(np.float64), res.V)
+    np.testing.assert_array_equal(r[:, posts].astype(np.int32), res.ref)
+
+
 def test_rows_rules_of_use(gpu, oracle):
     from paper_2305_02510_amd._lib import SnError
     Network = gpu
