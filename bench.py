@@ -375,8 +375,11 @@ def bench_bptt(args):
                            f"{prob.checkpoint} steps, dense delay-1 weights", "trials": B, "time_steps_per_run": T}}
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": None,
-                       "kernel": "k_bptt_part + k_bptt_fwd_epi + k_bptt_bwd_epi + k_bptt_wgrad (whole step)",
-                       "flops_per_step": flops}
+                       "kernel": "k_gemm_split + k_bptt_part + k_bptt_fwd_epi + k_bptt_bwd_epi + k_bptt_wgrad "
+                                 "(whole step)",
+                       "flops_per_step": flops,
+                       "note": "FP32-equivalent flops over the FP32 peak; the spike-operand products (forward spike "
+                               "term, W_rec gradient) run on bfloat16 matrix cores as three exact pieces"}
     if not args.no_cpu_baseline:
         import oracle
         orc = oracle.default()

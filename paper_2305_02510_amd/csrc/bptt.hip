@@ -442,21 +442,26 @@ __global__ __launch_bounds__(256) void k_bptt_bwd_epi(const BpttDev p, const flo
 }
 
 // dW[K][N] += A^T G over M rows: A [M][K], G [M][N] (row-major); rows
-// k >= kbase of dW only (grid y covers K - kbase).
+// k >= kbase of dW only (grid y covers K - kbase).  With mc > 0 the rows m
+// are split over gridDim.z in ranges of mc and part z is stored (not added)
+// at Pz + z (K - kbase) N, rows k - kbase, for k_add_parts.
 __global__ __launch_bounds__(256) void k_bptt_wgrad(int M, int K, int N, const float* __restrict__ A,
-                                                    const float* __restrict__ G, float* dW, int kbase) {
+                                                    const float* __restrict__ G, float* dW, int kbase, int mc,
+                                                    float* Pz) {
   __shared__ float As[2][64][kT64 + 4];  // row strides 68 and 80 words: the
   __shared__ float Bs[2][kT64][80];      // matrix-core operand reads are 2-way in the 32 banks
   const int col0 = 64 * blockIdx.x, row0 = kbase + 64 * blockIdx.y;  // columns of dW (j), rows of dW (k)
+  const int m0 = mc > 0 ? static_cast<int>(blockIdx.z) * mc : 0;
+  const int m1 = mc > 0 ? min(M, m0 + mc) : M;
   auto Aload = [&](int r, int m) -> float {  // (A^T)[row0 + r][m]
     const int k = row0 + r;
-    return (k < K && m < M) ? A[static_cast<size_t>(m) * K + k] : 0.f;
+    return (k < K && m < m1) ? A[static_cast<size_t>(m) * K + k] : 0.f;
   };
   auto Bload = [&](int m, int c) -> float {
     const int j = col0 + c;
-    return (m < M && j < N) ? G[static_cast<size_t>(m) * N + j] : 0.f;
+    return (m < m1 && j < N) ? G[static_cast<size_t>(m) * N + j] : 0.f;
   };
-  const Acc64 acc = tile_product64(0, M, Aload, Bload, As, Bs);
+  const Acc64 acc = tile_product64(m0, m1, Aload, Bload, As, Bs);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 #pragma unroll
@@ -467,8 +472,22 @@ __global__ __launch_bounds__(256) void k_bptt_wgrad(int M, int K, int N, const f
       for (int r = 0; r < 4; ++r) {
         const int k = row0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
         const int col = col0 + 32 * wc + 16 * jj + (lane & 15);
-        if (k < K && col < N) dW[static_cast<size_t>(k) * N + col] += acc.v[i][jj][r];
+        if (k < K && col < N) {
+          if (mc > 0)
+            Pz[(static_cast<size_t>(blockIdx.z) * (K - kbase) + (k - kbase)) * N + col] = acc.v[i][jj][r];
+          else
+            dW[static_cast<size_t>(k) * N + col] += acc.v[i][jj][r];
+        }
       }
+}
+
+// dst[i] += sum over z < nz of parts[z count + i], in order z = 0, 1, ...
+__global__ void k_add_parts(float* dst, const float* __restrict__ parts, int nz, size_t count) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float a = 0.f;
+  for (int z = 0; z < nz; ++z) a += parts[static_cast<size_t>(z) * count + i];
+  dst[i] += a;
 }
 
 __global__ void k_transpose(const float* __restrict__ src, float* dst, int n) {
@@ -514,6 +533,7 @@ namespace {
 struct WsLayout {
   size_t spikes, vckpt, sbuf, vbuf, useg, vseg, sseg, gseg, aseg, wrt, carry, sprev, junk, part, wsplit, sbf, xw, segt,
       total;
+  size_t part_floats;
 };
 
 // K split of a per-step product over about two workgroups per compute unit
@@ -521,18 +541,20 @@ struct WsLayout {
 struct KSplit {
   int kc, parts;
 };
-KSplit ksplit(int K, int N, int B) {
+KSplit ksplit(int K, int N, int B, int target = 512) {
   const int tiles = ((N + 63) / 64) * ((B + 63) / 64);
-  const int want = std::max(1, std::min(16, (512 + tiles - 1) / tiles));
+  const int want = std::max(1, std::min(16, (target + tiles - 1) / tiles));
   const int kc = std::max(kT64, (K + want * kT64 - 1) / (want * kT64) * kT64);
   return {kc, (K + kc - 1) / kc};
 }
 
 int pad64(int n) { return (n + 63) / 64 * 64; }
 
+constexpr int kHardSplitTarget = 512;  // workgroups of a hard-mode forward product
+
 // hard mode: spike parts of the forward product (contraction 3 Np) plus
 // the FP32 input part
-KSplit ksplit_hard(int N, int B) { return ksplit(3 * pad64(N), N, B); }
+KSplit ksplit_hard(int N, int B) { return ksplit(3 * pad64(N), N, B, kHardSplitTarget); }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -559,7 +581,8 @@ WsLayout ws_layout(const sn_bptt_desc& d) {
   const int pf = d.relaxed ? ksplit(static_cast<int>(N + Nin), static_cast<int>(N), static_cast<int>(B)).parts
                            : ksplit_hard(static_cast<int>(N), static_cast<int>(B)).parts;
   const int pb = ksplit(static_cast<int>(N), static_cast<int>(N), static_cast<int>(B)).parts;
-  L.part = take(static_cast<size_t>(std::max(pf, pb)) * bn);
+  L.part_floats = static_cast<size_t>(std::max(pf, pb)) * B * N;
+  L.part = take(L.part_floats * sizeof(float));
   const size_t Np = pad64(static_cast<int>(N));
   L.wsplit = take(d.relaxed ? 0 : N * 3 * Np * sizeof(uint16_t));
   L.sbf = take(d.relaxed ? 0 : 2 * B * Np * sizeof(uint16_t));
@@ -676,6 +699,7 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
   const dim3 epi(static_cast<unsigned>((bn + 255) / 256));
   const KSplit kf = ksplit(KA, N, B), kb = ksplit(N, N, B);
   float* part = at<float>(ws, L.part);
+  const size_t part_floats = L.part_floats;
   const int Np = pad64(N);
   const KSplit kh = ksplit_hard(N, B);
   const uint16_t* wsplit = at<uint16_t>(ws, L.wsplit);  // written by the forward pass from the same W
@@ -754,7 +778,7 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
     const int M = (t1 - t0) * B;
     if (d.relaxed) {
       hipLaunchKernelGGL(k_bptt_wgrad, dim3((N + 63) / 64, (KA + 63) / 64), dim3(256), 0, s, M, KA, N,
-                         at<float>(ws, L.aseg), at<float>(ws, L.gseg), dW, 0);
+                         at<float>(ws, L.aseg), at<float>(ws, L.gseg), dW, 0, 0, static_cast<float*>(nullptr));
       SN_TRY(hipGetLastError());
     } else {
       // W_rec rows: spikes (0 / 1) times the three bfloat16 pieces of g;
@@ -770,8 +794,22 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
                          static_cast<size_t>(0), 1);
       SN_TRY(hipGetLastError());
       if (Nin > 0) {
-        hipLaunchKernelGGL(k_bptt_wgrad, dim3((N + 63) / 64, (Nin + 63) / 64), dim3(256), 0, s, M, KA, N,
-                           at<float>(ws, L.aseg), at<float>(ws, L.gseg), dW, N);
+        // few output tiles: the rows m split over nz workgroups per tile,
+        // partial products in the part buffer, added in a fixed order
+        const size_t xcount = static_cast<size_t>(Nin) * N;
+        const int nz = static_cast<int>(std::min<size_t>(4, part_floats / xcount));  // parts that fit the buffer
+        if (nz >= 2) {
+          const int mc = (M + nz * kT64 - 1) / (nz * kT64) * kT64;
+          const int zz = (M + mc - 1) / mc;  // <= nz
+          hipLaunchKernelGGL(k_bptt_wgrad, dim3((N + 63) / 64, (Nin + 63) / 64, zz), dim3(256), 0, s, M, KA, N,
+                             at<float>(ws, L.aseg), at<float>(ws, L.gseg), dW, N, mc, part);
+          SN_TRY(hipGetLastError());
+          hipLaunchKernelGGL(k_add_parts, dim3(static_cast<unsigned>((xcount + 255) / 256)), dim3(256), 0, s,
+                             dW + static_cast<size_t>(N) * N, static_cast<const float*>(part), zz, xcount);
+        } else {
+          hipLaunchKernelGGL(k_bptt_wgrad, dim3((N + 63) / 64, (Nin + 63) / 64), dim3(256), 0, s, M, KA, N,
+                             at<float>(ws, L.aseg), at<float>(ws, L.gseg), dW, N, 0, static_cast<float*>(nullptr));
+        }
         SN_TRY(hipGetLastError());
       }
     }
