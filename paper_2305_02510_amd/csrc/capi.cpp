@@ -87,6 +87,7 @@ struct sn_net {
   bool stdp_on = false;
   StdpArgs stdp{};
   int32_t stdp_gen = 0;
+  uint64_t* stdp_hist = nullptr;  // [2][Npad] spike-history words of the plasticity kernel
   bool push_stale = false;
   int64_t nnz_loaded = 0;
   uint64_t* mailbox = nullptr;  // [D + 1][B][2G] tagged spike words
@@ -128,6 +129,15 @@ sn_status device_error(sn_net* n, hipError_t e, const char* what) {
     hipError_t e_ = (call);                                \
     if (e_ != hipSuccess) return device_error(net, e_, #call); \
   } while (0)
+
+// The cached graph holds kernel arguments by value (sizes, plans, rule
+// parameters); a new set of weights invalidates it.  Called after the stream
+// has been synchronized.
+void drop_graph(sn_net* n) {
+  if (n->graph) (void)hipGraphExecDestroy(n->graph);
+  n->graph = nullptr;
+  n->graph_path = -1;
+}
 
 sn_status check_usable(sn_net* n) {
   if (!n) return fail(SN_EINVAL, "network is NULL");
@@ -716,6 +726,7 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   }
   // the previous buffers may be in use by queued work
   SN_HIP(n, hipStreamSynchronize(n->stream));
+  drop_graph(n);
   dev_free(n, n->recs);
   dev_free(n, n->gptr);
   dev_free(n, n->gsplit);
@@ -770,6 +781,7 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->push_stale = false;
   n->nnz_loaded = nnz;
   n->stdp.recs = static_cast<Rec*>(n->recs);
+  stdp_chunks(n->layout.max_group_records, n->stdp.chunk, n->stdp.chunks);
   return SN_OK;
 }
 
@@ -853,6 +865,7 @@ sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const i
   if (!n->rows_loaded) {
     // queued work may still read the buffers dropped here
     SN_HIP(n, hipStreamSynchronize(n->stream));
+    drop_graph(n);
     void* r = dev_alloc(n, static_cast<size_t>(N) * pitch);
     if (!r) return fail(SN_ENOMEM, "cannot allocate %zu bytes of dense rows", static_cast<size_t>(N) * pitch);
     for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr}) {
@@ -991,6 +1004,11 @@ sn_status sn_run(sn_net* n, int32_t n_steps) {
     }
     case SN_PATH_STEP:
       SN_HIP(n, prepare_step_kernel(n->d));
+      if (n->stdp_on) {  // history words of the steps before this run, from the raster
+        StdpArgs a = n->stdp;
+        a.n = n->d;
+        SN_HIP(n, launch_hist_build(a, n->t, n->stream));
+      }
       st = run_per_step(n, SN_PATH_STEP, n->t, n_steps);
       if (st != SN_OK) return st;
       if (n->stdp_on) n->push_stale = true;
@@ -1105,6 +1123,12 @@ sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
   }
   a.w_min = desc->w_min == 0.f ? 0.f : desc->w_min;  // -0 would read as a filler mark
   a.w_max = desc->w_max == 0.f ? 0.f : desc->w_max;
+  if (!n->stdp_hist) {
+    n->stdp_hist = static_cast<uint64_t*>(dev_alloc(n, 2 * static_cast<size_t>(n->d.Npad) * sizeof(uint64_t)));
+    if (!n->stdp_hist) return fail(SN_ENOMEM, "cannot allocate the spike-history words");
+  }
+  a.hist = n->stdp_hist;
+  stdp_chunks(n->layout.max_group_records, a.chunk, a.chunks);
   SN_HIP(n, prepare_stdp_kernel());
   n->stdp = a;
   n->stdp_on = true;
@@ -1230,6 +1254,7 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->wt);
   dev_free(n, n->wt8);
   dev_free(n, n->rows8);
+  dev_free(n, n->stdp_hist);
   dev_free(n, n->orecs);
   dev_free(n, n->optr);
   dev_free(n, n->push_wg);

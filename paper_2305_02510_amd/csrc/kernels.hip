@@ -815,33 +815,46 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
 // launches); fillers (weight -0.0) are left alone.  Every change is a
 // function of spike times only, so records are independent.
 // ---------------------------------------------------------------------------
-// RING: the raster rows t - D - W + 1 .. t the rule can look at are first
-// copied into LDS (rows before step 0 as zeros), else read from the raster.
-constexpr int kStdpThreads = 1024;
-constexpr int kStdpUnroll = 4;  // records per thread loaded together
+// Spike times come from per-neuron history words: hist[p][i] bit k = spike
+// of neuron i at step T - k, where T = t - 1 for the buffer p = (t - 1) & 1
+// the kernel of step t reads.  H_t(i) = (H_{t-1}(i) << 1) | s_i(t), with
+// s_i(t) from the raster row t staged in LDS.  Then
+//   potentiation: the arrivals within the window are bits d .. d + W - 1 of
+//     H_t(pre); the latest is the lowest set bit;
+//   depression: an arrival at t is bit d of H_t(pre); the post spikes at
+//     t - 1 .. t - W are bits 1 .. W of H_t(post).
+// A record with d + W > 64 (its window leaves the 64-bit history) reads
+// the raster rows instead.  Workgroup (g, c) visits the records
+// c * chunk .. of group g; workgroups (g, 0) write H_t of the group's 64
+// neurons to the other buffer, for step t + 1.
 
-template <bool RING>
 __global__ __launch_bounds__(kStdpThreads) void k_stdp(const StdpArgs a, int t) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* rows = reinterpret_cast<uint64_t*>(smem);  // [D + W][G], row t - D - W + 1 + i at i
+  uint64_t* row_t = reinterpret_cast<uint64_t*>(smem);  // raster row t, G words
+  __shared__ uint64_t hpost[kGroup];                    // H_t of this group's neurons
   const DevNet& n = a.n;
   const int g = blockIdx.x;
-  const int beg = n.gptr[g], end = n.gptr[g + 1];
-  const int first = t - n.D - a.window + 1;
-  if (RING) {
-    const int nrows = n.D + a.window;
-    for (int i = threadIdx.x; i < nrows * n.G; i += blockDim.x) {
-      const int r = i / n.G, w = i - r * n.G;
-      rows[i] = first + r >= 0 ? n.raster[row_word(n, first + r, 0, w)] : 0ull;
-    }
-    __syncthreads();
+  const int gbeg = n.gptr[g], gend = n.gptr[g + 1];
+  const int beg = min(gend, gbeg + static_cast<int>(blockIdx.y) * a.chunk);
+  const int end = min(gend, beg + a.chunk);
+  const uint64_t* hprev = a.hist + static_cast<size_t>((t - 1) & 1) * n.Npad;
+  uint64_t* hcur = a.hist + static_cast<size_t>(t & 1) * n.Npad;
+  for (int w = threadIdx.x; w < n.G; w += blockDim.x) row_t[w] = n.raster[row_word(n, t, 0, w)];
+  __syncthreads();
+  if (threadIdx.x < kGroup) {
+    const uint32_t j = static_cast<uint32_t>(g) * kGroup + threadIdx.x;
+    const uint64_t h = (hprev[j] << 1) | ((row_t[g] >> threadIdx.x) & 1ull);
+    hpost[threadIdx.x] = h;
+    if (blockIdx.y == 0) hcur[j] = h;
   }
-  auto bit = [&](int tau, uint32_t neuron) -> uint32_t {
-    const int w = static_cast<int>(neuron >> 6);
-    const uint64_t word = RING ? rows[(tau - first) * n.G + w] : n.raster[row_word(n, tau, 0, w)];
-    return static_cast<uint32_t>(word >> (neuron & 63u)) & 1u;
+  __syncthreads();
+  const uint32_t wmask = (1u << a.window) - 1u;
+  auto hist_t = [&](uint32_t i) -> uint64_t {
+    return (hprev[i] << 1) | ((row_t[i >> 6] >> (i & 63u)) & 1ull);
   };
-  const uint64_t post_word = n.raster[row_word(n, t, 0, g)];
+  auto bit = [&](int tau, uint32_t neuron) -> uint32_t {  // raster bit, for windows beyond the history
+    return static_cast<uint32_t>(n.raster[row_word(n, tau, 0, static_cast<int>(neuron >> 6))] >> (neuron & 63u)) & 1u;
+  };
   for (int k0 = beg + static_cast<int>(threadIdx.x); k0 < end; k0 += kStdpUnroll * kStdpThreads) {
     Rec rr[kStdpUnroll];
 #pragma unroll
@@ -849,56 +862,92 @@ __global__ __launch_bounds__(kStdpThreads) void k_stdp(const StdpArgs a, int t) 
       const int k = k0 + u * kStdpThreads;
       rr[u] = k < end ? a.recs[k] : Rec{-0.f, 0u};
     }
+    uint64_t hp[kStdpUnroll];
 #pragma unroll
     for (int u = 0; u < kStdpUnroll; ++u) {
-    const int k = k0 + u * kStdpThreads;
-    const Rec r = rr[u];
-    if (k >= end || __float_as_uint(r.w) == 0x80000000u) continue;  // past the group, or a filler
-    const uint32_t pre = r.meta & 0xFFFFFu;
-    const int d = static_cast<int>((r.meta >> 20) & 63u) + 1;
-    const uint32_t pl = r.meta >> 26;
-    const uint32_t post = static_cast<uint32_t>(g) * kGroup + pl;
-    float change = 0.f;
-    if ((post_word >> pl) & 1ull) {
-      for (int lag = 0; lag < a.window; ++lag) {
-        const int tau = t - lag - d;
-        if (tau < 0) break;
-        if (bit(tau, pre)) {
-          change += a.ltp[lag];
-          break;
+      const int k = k0 + u * kStdpThreads;
+      const bool live = k < end && __float_as_uint(rr[u].w) != 0x80000000u;  // past the group, or a filler
+      hp[u] = live ? hist_t(rr[u].meta & 0xFFFFFu) : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kStdpUnroll; ++u) {
+      const int k = k0 + u * kStdpThreads;
+      const Rec r = rr[u];
+      if (k >= end || __float_as_uint(r.w) == 0x80000000u) continue;
+      const uint32_t pre = r.meta & 0xFFFFFu;
+      const int d = static_cast<int>((r.meta >> 20) & 63u) + 1;
+      const uint32_t pl = r.meta >> 26;
+      const uint64_t hq = hpost[pl];
+      float change = 0.f;
+      if (d + a.window <= 64) {
+        if (hq & 1ull) {
+          const uint32_t m = static_cast<uint32_t>(hp[u] >> d) & wmask;
+          if (m) change += a.ltp[__builtin_ctz(m)];
+        }
+        if ((hp[u] >> d) & 1ull) {
+          const uint32_t m = static_cast<uint32_t>(hq >> 1) & wmask;
+          if (m) change -= a.ltd[__builtin_ctz(m)];
+        }
+      } else {
+        const uint32_t post = static_cast<uint32_t>(g) * kGroup + pl;
+        if (hq & 1ull) {
+          for (int lag = 0; lag < a.window; ++lag) {
+            const int tau = t - lag - d;
+            if (tau < 0) break;
+            if (bit(tau, pre)) {
+              change += a.ltp[lag];
+              break;
+            }
+          }
+        }
+        if (t - d >= 0 && bit(t - d, pre)) {
+          for (int lag = 1; lag <= a.window; ++lag) {
+            if (t - lag < 0) break;
+            if (bit(t - lag, post)) {
+              change -= a.ltd[lag - 1];
+              break;
+            }
+          }
         }
       }
-    }
-    if (t - d >= 0 && bit(t - d, pre)) {
-      for (int lag = 1; lag <= a.window; ++lag) {
-        if (t - lag < 0) break;
-        if (bit(t - lag, post)) {
-          change -= a.ltd[lag - 1];
-          break;
-        }
-      }
-    }
-    const float w = fminf(fmaxf(r.w + change, a.w_min), a.w_max);
-    if (__float_as_uint(w) != __float_as_uint(r.w)) a.recs[k].w = w;
+      const float w = fminf(fmaxf(r.w + change, a.w_min), a.w_max);
+      if (__float_as_uint(w) != __float_as_uint(r.w)) a.recs[k].w = w;
     }
   }
 }
 
-constexpr size_t kStdpRingLimit = 64 * 1024;
+// History words before step t0: buffer (t0 - 1) & 1 gets, for every neuron,
+// bit k = spike at t0 - 1 - k (zero before step 0), from the raster.
+__global__ void k_hist_build(const StdpArgs a, int t0) {
+  const DevNet& n = a.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n.Npad) return;
+  uint64_t h = 0ull;
+  for (int k = 0; k < 64; ++k) {
+    const int tau = t0 - 1 - k;
+    if (tau < 0) break;
+    h |= ((n.raster[row_word(n, tau, 0, i >> 6)] >> (i & 63)) & 1ull) << k;
+  }
+  a.hist[static_cast<size_t>((t0 - 1) & 1) * n.Npad + i] = h;
+}
+
+constexpr size_t kStdpRowLimit = 128 * 1024;  // raster row of 2^20 neurons
 
 hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s) {
-  const size_t ring = static_cast<size_t>(a.n.D + a.window) * a.n.G * sizeof(uint64_t);
-  if (ring <= kStdpRingLimit) {
-    hipLaunchKernelGGL(k_stdp<true>, dim3(a.n.G), dim3(kStdpThreads), ring, s, a, t);
-  } else {
-    hipLaunchKernelGGL(k_stdp<false>, dim3(a.n.G), dim3(kStdpThreads), 0, s, a, t);
-  }
+  const size_t lds = static_cast<size_t>(a.n.G) * sizeof(uint64_t);
+  if (lds > kStdpRowLimit || !a.hist || a.chunk < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stdp, dim3(a.n.G, a.chunks), dim3(kStdpThreads), lds, s, a, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_build(const StdpArgs& a, int32_t t0, hipStream_t s) {
+  hipLaunchKernelGGL(k_hist_build, dim3((a.n.Npad + 255) / 256), dim3(256), 0, s, a, t0);
   return hipGetLastError();
 }
 
 hipError_t prepare_stdp_kernel() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stdp<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(kStdpRingLimit));
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stdp), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(kStdpRowLimit));
 }
 
 constexpr size_t kStepRingLimit = 64 * 1024;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -109,7 +110,17 @@ struct StdpArgs {
   float ltp[16];    // ltp[lag], lag = t - arrival < W
   float ltd[16];    // ltd[lag - 1], lag = t - post spike in 1..W
   float w_min, w_max;
+  uint64_t* hist;   // [2][Npad] spike-history words (bit k: spike k steps before)
+  int32_t chunk;    // records per workgroup (a group's records split over `chunks` workgroups)
+  int32_t chunks;
 };
+constexpr int kStdpThreads = 256;
+constexpr int kStdpUnroll = 4;  // records per thread loaded together
+// records of a group per plasticity workgroup, and workgroups per group
+inline void stdp_chunks(int32_t max_group_records, int32_t& chunk, int32_t& chunks) {
+  chunk = kStdpThreads * kStdpUnroll;
+  chunks = std::max(1, (max_group_records + chunk - 1) / chunk);
+}
 
 // Dense delay-1 weights for the matrix-core path, bfloat16, tiled for
 // v_mfma_f32_16x16x32_bf16.  K (pre-neurons) is padded to kpad, a multiple
@@ -218,6 +229,7 @@ hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
 hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
+hipError_t launch_hist_build(const StdpArgs& a, int32_t t0, hipStream_t s);
 hipError_t prepare_stdp_kernel();
 hipError_t prepare_step_kernel(const DevNet& n);
 hipError_t launch_dense_step(const DenseArgs& a, int32_t t, hipStream_t s);
