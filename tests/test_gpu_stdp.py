@@ -59,6 +59,17 @@ def test_stdp_small_nets(gpu, oracle, seed, n, window, chunks):
     check(net, res, *out[:4], f"seed={seed} n={n} window={window}")
 
 
+def test_stdp_long_delays(gpu, oracle):
+    """Delays up to 64 with window 8: records with d + W > 64 look past the
+    64-step history words and take the raster rows instead."""
+    net = wl.random_small(620, n=120, p=0.15, max_delay=64, steps=200, drive_p=0.15)
+    assert (net.delay.astype(int) + 8 > 64).any()
+    res = oracle.stdp(net, 8, LTP, LTD, -1.0, 1.5)
+    assert (res.weight != net.weight).any()
+    out = run_stdp(gpu, net, 8, -1.0, 1.5, [70, 130])
+    check(net, res, *out[:4], "long delays")
+
+
 def test_stdp_larger_net(gpu, oracle):
     """N = 3000, p = 0.02 (about 180k synapses), delays 1..16, 150 steps."""
     net = wl.large_sparse(21, n=3000, p=0.02, steps=150)
