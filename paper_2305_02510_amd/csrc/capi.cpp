@@ -261,13 +261,15 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
       } else if (path == SN_PATH_DENSE_ROWS) {
         RowsArgs a{n->d, static_cast<const int8_t*>(n->rows8), n->d.Npad, std::ldexp(1.f, -n->rows_e)};
         e = launch_dense_rows(a, t0 + k, s);
+      } else if (n->stdp_on) {
+        // the rule of step t - 1 is applied inside step t's kernel; the rule
+        // of the run's last step by the plasticity kernel
+        StdpArgs a = n->stdp;
+        a.n = n->d;
+        e = launch_step_stdp(a, t0 + k, k > 0 ? 1 : 0, s);
+        if (e == hipSuccess && k == steps - 1) e = launch_stdp(a, t0 + k, s);
       } else {
         e = launch_step(n->d, t0 + k, s);
-        if (e == hipSuccess && n->stdp_on) {
-          StdpArgs a = n->stdp;
-          a.n = n->d;
-          e = launch_stdp(a, t0 + k, s);
-        }
       }
       if (e != hipSuccess) return e;
     }

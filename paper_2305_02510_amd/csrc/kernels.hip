@@ -704,11 +704,17 @@ hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0
 // one global round trip; the source bit of row t - d is then an LDS read and
 // w is added into an LDS accumulator.  Wave 0 applies the neuron update and
 // writes the group's spike word.
+// STDP (one trial, plasticity on): with `apply`, the rule of step t - 1 (the
+// rule of k_stdp with T = t - 1, from the history words H_{t-1}) is applied
+// to every loaded record before its delivery, which then uses the new
+// weight; wave 0 writes H_t of its 64 neurons.  The rule of the last step of
+// a run is applied by k_stdp.
 // ---------------------------------------------------------------------------
-template <int WAVES, int U, bool RING>
-__global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
+template <int WAVES, int U, bool RING, bool STDP>
+__global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, const StdpArgs sa, int apply) {
   __shared__ float acc[kGroup];
   __shared__ float part[WAVES][kGroup];
+  __shared__ uint64_t hq_s[STDP ? kGroup : 1];  // H_{t-1} of this group's neurons
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);  // [D][2G]: row t - d at (d - 1)
   const int g = blockIdx.x;
@@ -734,6 +740,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
     amp = n.amp[j];
     R = n.refr[j];
     ew = n.ext[row_word(n, t, b, g)];
+    if (STDP) hq_s[lane] = sa.hist[static_cast<size_t>((t - 1) & 1) * n.Npad + j];
   }
   const int beg = n.gptr[g];
   const int end = n.gptr[g + 1];
@@ -758,7 +765,68 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
   }
   __syncthreads();
   float sum = 0.f;  // lane-owned records (record k of the group is in lane k mod 64)
+  const uint32_t wmask = STDP ? (1u << sa.window) - 1u : 0u;
   for (;;) {
+    if (STDP && apply) {  // rule of step T = t - 1 on the loaded records
+      const int T = t - 1;
+      const uint64_t* hprev = sa.hist + static_cast<size_t>(T & 1) * n.Npad;
+      uint64_t hp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool live = ok[u] && __float_as_uint(rr[u].w) != 0x80000000u;  // fillers keep -0.0
+        hp[u] = live ? hprev[rr[u].meta & 0xFFFFFu] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!ok[u] || __float_as_uint(rr[u].w) == 0x80000000u) continue;
+        const uint32_t m = rr[u].meta;
+        const uint32_t pre = m & 0xFFFFFu;
+        const int d = static_cast<int>((m >> 20) & 63u) + 1;
+        const uint32_t pl = m >> 26;
+        const uint64_t hq = hq_s[pl];
+        float change = 0.f;
+        if (d + sa.window <= 64) {
+          if (hq & 1ull) {
+            const uint32_t x = static_cast<uint32_t>(hp[u] >> d) & wmask;
+            if (x) change += sa.ltp[__builtin_ctz(x)];
+          }
+          if ((hp[u] >> d) & 1ull) {
+            const uint32_t x = static_cast<uint32_t>(hq >> 1) & wmask;
+            if (x) change -= sa.ltd[__builtin_ctz(x)];
+          }
+        } else {  // the window leaves the history words: raster rows
+          auto rbit = [&](int tau, uint32_t neuron) -> uint32_t {
+            return static_cast<uint32_t>(n.raster[row_word(n, tau, 0, static_cast<int>(neuron >> 6))] >>
+                                         (neuron & 63u)) & 1u;
+          };
+          const uint32_t post = static_cast<uint32_t>(g) * kGroup + pl;
+          if (hq & 1ull) {
+            for (int lag = 0; lag < sa.window; ++lag) {
+              const int tau = T - lag - d;
+              if (tau < 0) break;
+              if (rbit(tau, pre)) {
+                change += sa.ltp[lag];
+                break;
+              }
+            }
+          }
+          if (T - d >= 0 && rbit(T - d, pre)) {
+            for (int lag = 1; lag <= sa.window; ++lag) {
+              if (T - lag < 0) break;
+              if (rbit(T - lag, post)) {
+                change -= sa.ltd[lag - 1];
+                break;
+              }
+            }
+          }
+        }
+        const float w = fminf(fmaxf(rr[u].w + change, sa.w_min), sa.w_max);
+        if (__float_as_uint(w) != __float_as_uint(rr[u].w)) {
+          sa.recs[base + u * 64 + lane].w = w;
+          rr[u].w = w;
+        }
+      }
+    }
     uint32_t bit[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -801,6 +869,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t) {
     n.V[sj] = V;
     n.ref[sj] = static_cast<uint8_t>(ref);
     if (lane == 0) n.raster[row_word(n, t, b, g)] = sw;
+    if (STDP) sa.hist[static_cast<size_t>(t & 1) * n.Npad + j] = (hq_s[lane] << 1) | (s ? 1ull : 0ull);
   }
 }
 
@@ -954,13 +1023,13 @@ constexpr size_t kStepRingLimit = 64 * 1024;
 
 static size_t step_ring_bytes(const DevNet& n) { return static_cast<size_t>(n.D) * 2 * n.G * sizeof(uint32_t); }
 
-template <int WAVES, int U>
-static hipError_t launch_step_t(const DevNet& n, int32_t t, hipStream_t s) {
+template <int WAVES, int U, bool STDP>
+static hipError_t launch_step_t(const DevNet& n, int32_t t, const StdpArgs& sa, int apply, hipStream_t s) {
   const size_t ring = step_ring_bytes(n);
   if (ring <= kStepRingLimit) {
-    hipLaunchKernelGGL((k_step<WAVES, U, true>), dim3(n.G, n.B), dim3(WAVES * 64), ring, s, n, t);
+    hipLaunchKernelGGL((k_step<WAVES, U, true, STDP>), dim3(n.G, n.B), dim3(WAVES * 64), ring, s, n, t, sa, apply);
   } else {
-    hipLaunchKernelGGL((k_step<WAVES, U, false>), dim3(n.G, n.B), dim3(WAVES * 64), 0, s, n, t);
+    hipLaunchKernelGGL((k_step<WAVES, U, false, STDP>), dim3(n.G, n.B), dim3(WAVES * 64), 0, s, n, t, sa, apply);
   }
   return hipGetLastError();
 }
@@ -968,9 +1037,12 @@ static hipError_t launch_step_t(const DevNet& n, int32_t t, hipStream_t s) {
 hipError_t prepare_step_kernel(const DevNet& n) {
   const size_t ring = step_ring_bytes(n);
   if (ring > kStepRingLimit) return hipSuccess;
-  const void* fns[] = {reinterpret_cast<const void*>(&k_step<16, 8, true>),
-                       reinterpret_cast<const void*>(&k_step<4, 8, true>),
-                       reinterpret_cast<const void*>(&k_step<1, 4, true>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_step<16, 8, true, false>),
+                       reinterpret_cast<const void*>(&k_step<4, 8, true, false>),
+                       reinterpret_cast<const void*>(&k_step<1, 4, true, false>),
+                       reinterpret_cast<const void*>(&k_step<16, 8, true, true>),
+                       reinterpret_cast<const void*>(&k_step<4, 8, true, true>),
+                       reinterpret_cast<const void*>(&k_step<1, 4, true, true>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(ring));
     if (e != hipSuccess) return e;
@@ -981,9 +1053,19 @@ hipError_t prepare_step_kernel(const DevNet& n) {
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s) {
   // enough waves per group that every lane has its U records in one pass
   const int per_group = n.G > 0 ? (static_cast<int>(n.nnz / n.G) + 1) : 1;
-  if (per_group > 4 * 64 * 8) return launch_step_t<16, 8>(n, t, s);
-  if (per_group > 64 * 4) return launch_step_t<4, 8>(n, t, s);
-  return launch_step_t<1, 4>(n, t, s);
+  const StdpArgs none{};
+  if (per_group > 4 * 64 * 8) return launch_step_t<16, 8, false>(n, t, none, 0, s);
+  if (per_group > 64 * 4) return launch_step_t<4, 8, false>(n, t, none, 0, s);
+  return launch_step_t<1, 4, false>(n, t, none, 0, s);
+}
+
+hipError_t launch_step_stdp(const StdpArgs& a, int32_t t, int apply, hipStream_t s) {
+  const DevNet& n = a.n;
+  if (n.B != 1 || !a.hist) return hipErrorInvalidValue;
+  const int per_group = n.G > 0 ? (static_cast<int>(n.nnz / n.G) + 1) : 1;
+  if (per_group > 4 * 64 * 8) return launch_step_t<16, 8, true>(n, t, a, apply, s);
+  if (per_group > 64 * 4) return launch_step_t<4, 8, true>(n, t, a, apply, s);
+  return launch_step_t<1, 4, true>(n, t, a, apply, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -230,6 +230,8 @@ hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps,
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
 hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_hist_build(const StdpArgs& a, int32_t t0, hipStream_t s);
+// per-step kernel with plasticity: applies the rule of step t - 1 when apply != 0
+hipError_t launch_step_stdp(const StdpArgs& a, int32_t t, int apply, hipStream_t s);
 hipError_t prepare_stdp_kernel();
 hipError_t prepare_step_kernel(const DevNet& n);
 hipError_t launch_dense_step(const DenseArgs& a, int32_t t, hipStream_t s);
