@@ -13,7 +13,7 @@
 // v_mfma_f32_16x16x32_bf16 with the weight fragment shared by the four.  The
 // spike operand comes from the bit raster: one 32-bit word of a trial's bits
 // feeds four MFMA steps (see the K order in DenseArgs) and each byte is
-// expanded to eight bfloat16 0/1 values in registers (expand_bits).  The
+// expanded to eight bfloat16 0/1 values through a 256-entry LDS table.  The
 // four partial products are summed in LDS and the fused LIF update of §2.1
 // writes V, the refractory counters and 16 spike bits per trial.
 #include <hip/hip_runtime.h>
