@@ -87,3 +87,31 @@ def test_pack_unpack_roundtrip():
         assert np.array_equal(unpack_bits(w, n), x)
         j = n - 1
         assert (w[..., j // 32] >> (j % 32) & 1 == x[..., j]).all()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no CPU fallback: without the built library the binding refuses to load
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        _lib.load()
+
+
+def test_network_needs_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2305_02510_amd import Network
+    with pytest.raises(RuntimeError, match="no GPU"):
+        Network(10)
+
+
+def test_package_never_uses_the_oracle():
+    # the product path shares no code with the oracle and never imports it
+    pkg = os.path.join(ROOT, "paper_2305_02510_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f), encoding="utf-8").read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, flags=re.M), f
+                assert "lif_oracle" not in text and "liboracle" not in text, f
