@@ -551,6 +551,7 @@ KSplit ksplit(int K, int N, int B, int target = 512) {
 int pad64(int n) { return (n + 63) / 64 * 64; }
 
 constexpr int kHardSplitTarget = 512;  // workgroups of a hard-mode forward product
+constexpr int kBwdSplitTarget = 512;   // workgroups of a backward product g W_rec^T
 
 // hard mode: spike parts of the forward product (contraction 3 Np) plus
 // the FP32 input part
@@ -580,7 +581,7 @@ WsLayout ws_layout(const sn_bptt_desc& d) {
   L.junk = take(bn);
   const int pf = d.relaxed ? ksplit(static_cast<int>(N + Nin), static_cast<int>(N), static_cast<int>(B)).parts
                            : ksplit_hard(static_cast<int>(N), static_cast<int>(B)).parts;
-  const int pb = ksplit(static_cast<int>(N), static_cast<int>(N), static_cast<int>(B)).parts;
+  const int pb = ksplit(static_cast<int>(N), static_cast<int>(N), static_cast<int>(B), kBwdSplitTarget).parts;
   L.part_floats = static_cast<size_t>(std::max(pf, pb)) * B * N;
   L.part = take(L.part_floats * sizeof(float));
   const size_t Np = pad64(static_cast<int>(N));
@@ -697,7 +698,7 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
   const size_t bn = static_cast<size_t>(B) * N;
   const dim3 grid64((N + 63) / 64, (B + 63) / 64);
   const dim3 epi(static_cast<unsigned>((bn + 255) / 256));
-  const KSplit kf = ksplit(KA, N, B), kb = ksplit(N, N, B);
+  const KSplit kf = ksplit(KA, N, B), kb = ksplit(N, N, B, kBwdSplitTarget);
   float* part = at<float>(ws, L.part);
   const size_t part_floats = L.part_floats;
   const int Np = pad64(N);
