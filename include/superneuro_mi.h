@@ -127,8 +127,12 @@ sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc,
  * delay in [1, D].  Duplicate (pre, post) pairs act as separate synapses
  * (their weights add); self-synapses are allowed.  nnz may be 0.  Replaces
  * any earlier synapses; the simulation state is kept.  Arrays are read during
- * the call only.  Errors: SN_EINVAL (null arrays with nnz > 0, non-finite w),
- * SN_ERANGE (index or delay out of range), SN_ENOMEM, SN_EDEVICE. */
+ * the call only.  On the device the synapses are grouped by 64 post-neurons
+ * and padded with filler records (about 1.2 records per synapse for random
+ * nets, more for skewed in-degrees); the padded count must stay below 2^31.
+ * Errors: SN_EINVAL (null arrays with nnz > 0, non-finite w), SN_ERANGE
+ * (index or delay out of range, nnz >= 2^31, or the padded count >= 2^31),
+ * SN_ENOMEM (the network is unchanged), SN_EDEVICE. */
 sn_status sn_load_weights_delays(sn_net* net, int64_t nnz, const int32_t* pre, const int32_t* post,
                                  const float* w, const uint8_t* delay);
 
@@ -280,14 +284,16 @@ sn_status sn_get_progress(sn_net* net, int32_t* t, int32_t* path);
 typedef struct sn_batch sn_batch;
 
 /* Plans a batch over nets[0 .. count-1].  Errors: SN_EINVAL (null or
- * duplicate networks), SN_ESTATE (a network without synapses or poisoned),
+ * duplicate networks), SN_ESTATE (a network without a synapse list, with
+ * plasticity on -- a batch does not apply the rule -- or poisoned),
  * SN_ERANGE (a network outside the limits, or count outside [1, 65536]),
  * SN_ENOMEM, SN_EDEVICE. */
 sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out);
 
 /* Advances every network of the batch by n_steps steps, asynchronously on
- * the batch's stream.  Errors: SN_ERANGE, SN_ENOMEM, SN_EDEVICE (poisons the
- * batch and its networks). */
+ * the batch's stream.  Errors: SN_ESTATE (as sn_batch_create: plasticity was
+ * turned on or dense rows loaded since), SN_ERANGE, SN_ENOMEM, SN_EDEVICE
+ * (poisons the batch and its networks). */
 sn_status sn_batch_run(sn_batch* batch, int32_t n_steps);
 
 /* Frees the batch (not its networks).  NULL is ignored. */

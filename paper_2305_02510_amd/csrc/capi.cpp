@@ -212,18 +212,36 @@ SlicePlan plan_persist(const DevNet& d, const HostLayout& L, int32_t slices_req)
   return p;
 }
 
-sn_status upload_plan(sn_net* n, sn_net::DevPlan& dp, const SlicePlan& p) {
+// Device slice table of a plan (NULL for a plan that cannot run).  `bad` is
+// set when the allocation fails.
+void* alloc_plan(sn_net* n, const SlicePlan& p, bool& bad) {
+  if (p.P <= 0) return nullptr;
+  void* wg = dev_alloc(n, p.wg_group.size() * sizeof(int32_t));
+  if (!wg) bad = true;
+  return wg;
+}
+
+// Installs plan p with its table `wg` (from alloc_plan), freeing the old one.
+// The caller has synchronized the stream when queued work may read the old one.
+sn_status install_plan(sn_net* n, sn_net::DevPlan& dp, const SlicePlan& p, void* wg) {
   dev_free(n, dp.wg);
-  dp.wg = nullptr;
+  dp.wg = wg;
   dp.host = p;
   dp.ok = p.P > 0;
   if (!dp.ok) return SN_OK;
-  const std::vector<int32_t>& buf = p.wg_group;
-  dp.wg = dev_alloc(n, buf.size() * sizeof(int32_t));
-  if (!dp.wg) return fail(SN_ENOMEM, "cannot allocate slice tables");
-  SN_HIP(n, hipMemcpyAsync(dp.wg, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
-  SN_HIP(n, hipStreamSynchronize(n->stream));
+  SN_HIP(n, hipMemcpyAsync(dp.wg, p.wg_group.data(), p.wg_group.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           n->stream));
+  SN_HIP(n, hipStreamSynchronize(n->stream));  // the host table may die after return
   return SN_OK;
+}
+
+// Replaces one plan; on ENOMEM the old plan stays.
+sn_status upload_plan(sn_net* n, sn_net::DevPlan& dp, const SlicePlan& p) {
+  bool bad = false;
+  void* wg = alloc_plan(n, p, bad);
+  if (bad) return fail(SN_ENOMEM, "cannot allocate slice tables");
+  SN_HIP(n, hipStreamSynchronize(n->stream));  // queued launches may read the old table
+  return install_plan(n, dp, p, wg);
 }
 
 SimArgs sim_args(sn_net* n, const sn_net::DevPlan& dp) {
@@ -409,6 +427,7 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     if (!n) return fail(SN_EINVAL, "network %d is NULL", k);
     if (n->poisoned) return fail(SN_ESTATE, "network %d is poisoned", k);
     if (!n->synapses_loaded) return fail(SN_ESTATE, "network %d has no synapses", k);
+    if (n->stdp_on) return fail(SN_ESTATE, "network %d has plasticity on, which a batch does not apply", k);
     if (n->device != v[0]->device) return fail(SN_EINVAL, "networks are on different devices");
     if (batch_lds_bytes(n->d, 1) > 96 * 1024) return fail(SN_ERANGE, "network %d: spike ring too large for a batch", k);
   }
@@ -518,6 +537,8 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
   for (sn_net* n : bt->nets) {
     sn_status st = check_usable(n);
     if (st != SN_OK) return st;
+    if (n->stdp_on) return fail(SN_ESTATE, "a network of the batch has plasticity on, which a batch does not apply");
+    if (!n->synapses_loaded) return fail(SN_ESTATE, "a network of the batch has no synapse list (dense rows?)");
     if (static_cast<int64_t>(n->t) + n_steps > INT32_MAX) return fail(SN_ERANGE, "step counter overflows");
   }
   auto poison = [&](hipError_t e, const char* what) {
@@ -717,51 +738,56 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   }
   if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
   HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay);
+  if (L.too_large)
+    return fail(SN_ERANGE, "%lld synapses need more than 2^31 - 1 records with the layout's fillers",
+                static_cast<long long>(nnz));
+  HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
+  SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
+  if (!fit_plan(n->d, one)) one.P = 0;
+  SlicePlan many = plan_persist(n->d, L, n->slices_req);
+  // every new buffer is allocated before an old one is freed, so ENOMEM
+  // leaves the network as it was
   void* recs = dev_alloc(n, L.recs.size() * sizeof(Rec));
   void* gptr = dev_alloc(n, L.gptr.size() * sizeof(int32_t));
   void* gsplit = dev_alloc(n, L.gsplit.size() * sizeof(int32_t));
-  if (!recs || !gptr || !gsplit) {
-    dev_free(n, recs);
-    dev_free(n, gptr);
-    dev_free(n, gsplit);
+  void* orecs = dev_alloc(n, H.orecs.size() * sizeof(Rec));
+  void* optr = dev_alloc(n, H.optr.size() * sizeof(int32_t));
+  bool bad = !recs || !gptr || !gsplit || !orecs || !optr;
+  void* wg_one = alloc_plan(n, one, bad);
+  void* wg_many = alloc_plan(n, many, bad);
+  if (bad) {
+    for (void* p : {recs, gptr, gsplit, orecs, optr, wg_one, wg_many}) dev_free(n, p);
     return fail(SN_ENOMEM, "cannot allocate synapse records");
   }
   // the previous buffers may be in use by queued work
   SN_HIP(n, hipStreamSynchronize(n->stream));
   drop_graph(n);
-  dev_free(n, n->recs);
-  dev_free(n, n->gptr);
-  dev_free(n, n->gsplit);
+  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr}) {
+    dev_free(n, *p);
+    *p = nullptr;
+  }
   n->recs = recs;
   n->gptr = gptr;
   n->gsplit = gsplit;
+  n->orecs = orecs;
+  n->optr = optr;
+  n->d.recs = static_cast<const Rec*>(recs);
+  n->d.gptr = static_cast<const int32_t*>(gptr);
+  n->d.gsplit = static_cast<const int32_t*>(gsplit);
+  n->d.nnz = nnz;
+  // from here on a failure is a device error, which poisons the network
   if (!L.recs.empty())
     SN_HIP(n, hipMemcpyAsync(recs, L.recs.data(), L.recs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipMemcpyAsync(gptr, L.gptr.data(), L.gptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipMemcpyAsync(gsplit, L.gsplit.data(), L.gsplit.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+  if (!H.orecs.empty())
+    SN_HIP(n, hipMemcpyAsync(orecs, H.orecs.data(), H.orecs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
+  SN_HIP(n, hipMemcpyAsync(optr, H.optr.data(), H.optr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipStreamSynchronize(n->stream));  // host vectors die at return
-  n->d.recs = static_cast<const Rec*>(recs);
-  n->d.gptr = static_cast<const int32_t*>(gptr);
-  n->d.gsplit = static_cast<const int32_t*>(gsplit);
-  {
-    HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
-    void* orecs = dev_alloc(n, H.orecs.size() * sizeof(Rec));
-    void* optr = dev_alloc(n, H.optr.size() * sizeof(int32_t));
-    if (!orecs || !optr) {
-      dev_free(n, orecs);
-      dev_free(n, optr);
-      return fail(SN_ENOMEM, "cannot allocate out-going synapse records");
-    }
-    dev_free(n, n->orecs);
-    dev_free(n, n->optr);
-    n->orecs = orecs;
-    n->optr = optr;
-    if (!H.orecs.empty())
-      SN_HIP(n, hipMemcpyAsync(orecs, H.orecs.data(), H.orecs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
-    SN_HIP(n, hipMemcpyAsync(optr, H.optr.data(), H.optr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
-    SN_HIP(n, hipStreamSynchronize(n->stream));
-  }
-  n->d.nnz = nnz;
+  st = install_plan(n, n->small, one, wg_one);
+  if (st != SN_OK) return st;
+  st = install_plan(n, n->persist, many, wg_many);
+  if (st != SN_OK) return st;
   n->synapses_loaded = true;
   dev_free(n, n->rows8);
   n->rows8 = nullptr;
@@ -773,12 +799,6 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   dev_free(n, n->wt8);
   n->wt8 = nullptr;
   n->dense_loaded = false;
-  SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
-  if (!fit_plan(n->d, one)) one.P = 0;
-  st = upload_plan(n, n->small, one);
-  if (st != SN_OK) return st;
-  st = upload_plan(n, n->persist, plan_persist(n->d, L, n->slices_req));
-  if (st != SN_OK) return st;
   n->layout = std::move(L);
   n->push_stale = false;
   n->nnz_loaded = nnz;

@@ -16,6 +16,7 @@
 // multiple of 64 records, so record k of a group sits in lane
 // (k - gptr[g]) mod 64.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -119,6 +120,10 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
         }
       }
       for (; count % kGroup != 0; ++count) filler(fill_delay, static_cast<uint32_t>(count % kGroup));
+    }
+    if (L.recs.size() > static_cast<size_t>(INT32_MAX)) {  // offsets are 32-bit on the device
+      L.too_large = true;
+      return L;
     }
     L.max_group_records = std::max<int32_t>(L.max_group_records, static_cast<int32_t>(L.recs.size() - L.gptr[g]));
   }

@@ -43,6 +43,9 @@ struct HostLayout {
   std::vector<int32_t> gptr;    // [G + 1] record offset of every group
   std::vector<int32_t> gsplit;  // [G] first delay-1 record of every group
   int32_t max_group_records = 0;
+  // set when the records with fillers would pass INT32_MAX (offsets are
+  // 32-bit on the device); the other fields are then incomplete
+  bool too_large = false;
 };
 
 

@@ -104,3 +104,24 @@ def test_stdp_rules_of_use(gpu, oracle):
     g = gpu.from_workload(net)
     assert np.array_equal(g.read_weights(), net.weight.astype(np.float32))
     g.close()
+
+
+def test_batch_refuses_plasticity(gpu, oracle):
+    """A batch does not apply the rule, so it refuses a net with plasticity
+    on, both when planned and when the rule is turned on afterwards."""
+    from paper_2305_02510_amd import Batch
+    from paper_2305_02510_amd._lib import SnError
+    a = gpu.from_workload(wl.random_small(612, n=60, p=0.1, max_delay=3, steps=20))
+    b = gpu.from_workload(wl.random_small(613, n=90, p=0.1, max_delay=2, steps=20))
+    b.set_stdp(4, LTP, LTD, -1.0, 1.5)
+    with pytest.raises(SnError, match="SN_ESTATE"):
+        Batch([a, b])
+    b.stdp_off()
+    batch = Batch([a, b])
+    batch.run(5)
+    b.set_stdp(4, LTP, LTD, -1.0, 1.5)
+    with pytest.raises(SnError, match="SN_ESTATE"):
+        batch.run(5)
+    batch.close()
+    a.close()
+    b.close()
