@@ -223,6 +223,30 @@ def _bptt(self, W_rec, W_in, x, target, theta=1.0, leak=0.0625, reset=0.0, slope
 
 Oracle.bptt = _bptt
 
+def host_workers() -> int:
+    """Threads for fanning independent oracle runs (trials, nets, column
+    chunks) out over the host's cores: the cores this process may use, at
+    most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover - non-Linux hosts
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def fan_out(fn, items, workers: Optional[int] = None) -> list:
+    """[fn(x) for x in items], the calls spread over host threads.  Each call
+    is one single-threaded oracle run; ctypes releases the interpreter lock
+    while the C code runs, so the calls proceed in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+    items = list(items)
+    w = max(1, min(workers or host_workers(), len(items) or 1))
+    if w == 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(w) as ex:
+        return list(ex.map(fn, items))
+
+
 _default: Optional[Oracle] = None
 
 

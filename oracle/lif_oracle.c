@@ -274,27 +274,39 @@ int or_lif_columns(int32_t N, int32_t B, int32_t T, int32_t S, const int32_t* po
         if (posts[k] < 0 || posts[k] >= N) return OR_EINVAL;
     int exact = 1;
     if (check_exact && !check_params(N, theta, leak, reset, refractory, amplitude)) exact = 0;
+    /* the neurons that spiked at every step, in ascending order, so the sum
+     * over them visits the same terms as a scan of the whole history row */
+    size_t total = 0;
+    for (size_t q = 0; q < (size_t)B * T * N; ++q) total += history[q] != 0;
+    int32_t* list = (int32_t*)malloc((total + 1) * sizeof(int32_t));
+    size_t* first = (size_t*)malloc(((size_t)B * T + 1) * sizeof(size_t));
+    if (!list || !first) { free(list); free(first); return OR_ENOMEM; }
+    total = 0;
+    for (size_t bt = 0; bt < (size_t)B * T; ++bt) {
+        first[bt] = total;
+        for (int32_t i = 0; i < N; ++i)
+            if (history[bt * N + i]) list[total++] = i;
+    }
+    first[(size_t)B * T] = total;
     for (int32_t k = 0; k < S; ++k) {
         const int32_t j = posts[k];
         const double* w = wcol + (size_t)k * N;
         double in_abs = 0.0;
         for (int32_t i = 0; i < N; ++i) {
-            if (!isfinite(w[i])) return OR_EINVAL;
+            if (!isfinite(w[i])) { free(list); free(first); return OR_EINVAL; }
             if (check_exact && w[i] != 0.0 && !on_grid(w[i])) exact = 0;
             in_abs += fabs(w[i]);
         }
         for (int32_t b = 0; b < B; ++b) {
-            const uint8_t* hb = history + (size_t)b * T * N;
             const uint8_t* xb = ext + (size_t)b * T * N;
             double V = reset[j];
             int32_t ref = 0;
             for (int32_t t = 0; t < T; ++t) {
                 double U = apply_leak(V, reset[j], leak[j]);
                 if (check_exact && !(fabs(U) + in_abs + fabs(amplitude[j]) < EXACT_LIMIT)) exact = 0;
-                if (t > 0) {
-                    const uint8_t* sp = hb + (size_t)(t - 1) * N;
-                    for (int32_t i = 0; i < N; ++i)
-                        if (sp[i]) U += w[i];
+                if (t > 0) {  /* neurons that spiked at t - 1 */
+                    const size_t bt = (size_t)b * T + (t - 1);
+                    for (size_t q = first[bt]; q < first[bt + 1]; ++q) U += w[list[q]];
                 }
                 if (xb[(size_t)t * N + j]) U += amplitude[j];
                 spikes[((size_t)b * T + t) * S + k] =
@@ -304,6 +316,8 @@ int or_lif_columns(int32_t N, int32_t B, int32_t T, int32_t S, const int32_t* po
             ref_out[(size_t)b * S + k] = ref;
         }
     }
+    free(list);
+    free(first);
     return exact ? OR_OK : OR_NONEXACT;
 }
 

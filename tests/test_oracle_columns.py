@@ -62,8 +62,8 @@ def pin_columns_single_arrival(orc):
 COLUMN_PINS = [pin_columns_match_dense, pin_columns_single_arrival]
 
 COLUMN_MUTANTS = {
-    "same_step_history": ("const uint8_t* sp = hb + (size_t)(t - 1) * N;",
-                          "const uint8_t* sp = hb + (size_t)t * N;"),
+    "same_step_history": ("const size_t bt = (size_t)b * T + (t - 1);",
+                          "const size_t bt = (size_t)b * T + t;"),
     "external_of_slot": ("if (xb[(size_t)t * N + j]) U += amplitude[j];",
                          "if (xb[(size_t)t * N + k]) U += amplitude[j];"),
     "no_leak": ("double U = apply_leak(V, reset[j], leak[j]);", "double U = V;"),
