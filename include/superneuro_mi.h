@@ -336,6 +336,23 @@ size_t sn_bptt_workspace_bytes(const sn_bptt_desc* d);
 sn_status sn_bptt_forward(const sn_bptt_desc* d, const float* W_cat, const float* x, float* counts,
                           void* workspace, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward pass of sn_bptt_forward, same arguments and results, with its
+ * workspace in a device buffer the library holds instead of a caller's.  The
+ * call allocates nothing.  The buffer is SN_BPTT_NOALLOC_WORKSPACE_BYTES on
+ * every device the library runs on, kept until the process ends; a
+ * descriptor whose sn_bptt_workspace_bytes exceeds it gets SN_ERANGE.  Every
+ * call on a device uses that device's one buffer, so calls that overlap on
+ * one device (different streams or host threads) race and give undefined
+ * counts; order them on one stream.  Only counts are produced: the buffer
+ * is not kept for a backward pass.  Work is issued on hip_stream, which
+ * must belong to the current device.
+ * Errors: SN_EINVAL (null pointer, bad descriptor), SN_ERANGE, SN_EDEVICE. */
+#define SN_BPTT_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+sn_status sn_bptt_forward_noalloc(const sn_bptt_desc* d, const float* W_cat, const float* x, float* counts,
+                                  void* hip_stream);
+
 /* Backward pass after sn_bptt_forward with the same inputs and workspace:
  * given dL/dcounts [B][N], writes dL/dW_cat [N + Nin][N].
  * Errors: SN_EINVAL, SN_EDEVICE. */

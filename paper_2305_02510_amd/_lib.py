@@ -23,7 +23,7 @@ EXPORTS = [
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_autotune", "sn_get_progress", "sn_destroy_network",
     "sn_last_error", "sn_set_stdp", "sn_read_weights",
     "sn_batch_create", "sn_batch_run", "sn_batch_destroy",
-    "sn_bptt_workspace_bytes", "sn_bptt_forward", "sn_bptt_backward",
+    "sn_bptt_workspace_bytes", "sn_bptt_forward", "sn_bptt_backward", "sn_bptt_forward_noalloc",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -28,6 +28,8 @@ def _bind(lib):
     lib.sn_bptt_forward.restype = ctypes.c_int32
     lib.sn_bptt_backward.argtypes = [ctypes.POINTER(SnBpttDesc), P, P, P, P, P, P]
     lib.sn_bptt_backward.restype = ctypes.c_int32
+    lib.sn_bptt_forward_noalloc.argtypes = [ctypes.POINTER(SnBpttDesc), P, P, P, P]
+    lib.sn_bptt_forward_noalloc.restype = ctypes.c_int32
     lib._bptt_bound = True
     return lib
 

@@ -24,11 +24,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/superneuro_mi.h"
 #include "sn_internal.h"
 
 namespace snmi {
+
+// Forward workspace of sn_bptt_forward_noalloc, for callers that cannot
+// allocate: one copy on every device the library runs on, alive until the
+// process ends, shared by every call on that device.  Host code never passes
+// this name to a kernel (on the host it is only a stand-in for the symbol):
+// it uses the device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[SN_BPTT_NOALLOC_WORKSPACE_BYTES];
 
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
@@ -686,6 +694,32 @@ hipError_t bptt_forward(const sn_bptt_desc& d, const float* W, const float* x, f
                             hipMemcpyDeviceToDevice, s));
   }
   return hipSuccess;
+}
+
+hipError_t bptt_forward_noalloc(const sn_bptt_desc& d, const float* W, const float* x, float* counts, hipStream_t s) {
+  // the scratch array's address on the current device, looked up once per
+  // device with that device current (each device holds its own copy)
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  SN_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+      void* p = nullptr;
+      SN_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      addr[dev] = p;
+    }
+    ws = addr[dev];
+  }
+  // the forward writes every workspace word before reading it (counts are
+  // filled with zeros, the bfloat16 spike rows cleared by a kernel, every
+  // other buffer written by the step that reads it), so what an earlier call
+  // left in the scratch array does not matter
+  return bptt_forward(d, W, x, counts, ws, s);
 }
 
 hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, const float* dcounts, const void* ws_c,

@@ -617,6 +617,19 @@ sn_status sn_bptt_forward(const sn_bptt_desc* d, const float* W_cat, const float
   return SN_OK;
 }
 
+sn_status sn_bptt_forward_noalloc(const sn_bptt_desc* d, const float* W_cat, const float* x, float* counts,
+                                  void* hip_stream) {
+  if (!bptt_desc_ok(d)) return fail(SN_EINVAL, "invalid BPTT descriptor (N must be a positive multiple of 32)");
+  if (!W_cat || !x || !counts) return fail(SN_EINVAL, "null pointer");
+  const size_t need = bptt_workspace_bytes(*d);
+  if (need > static_cast<size_t>(SN_BPTT_NOALLOC_WORKSPACE_BYTES))
+    return fail(SN_ERANGE, "the forward needs %zu bytes of workspace, above the %zu of the library's buffer", need,
+                static_cast<size_t>(SN_BPTT_NOALLOC_WORKSPACE_BYTES));
+  const hipError_t e = bptt_forward_noalloc(*d, W_cat, x, counts, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(SN_EDEVICE, "BPTT forward (library workspace): %s", hipGetErrorString(e));
+  return SN_OK;
+}
+
 sn_status sn_bptt_backward(const sn_bptt_desc* d, const float* W_cat, const float* x, const float* dcounts,
                            const void* workspace, float* dW_cat, void* hip_stream) {
   if (!bptt_desc_ok(d)) return fail(SN_EINVAL, "invalid BPTT descriptor (N must be a positive multiple of 32)");

@@ -216,6 +216,9 @@ constexpr int kBatchMaxGroups = 24;  // groups per slice: 8 waves x 3 groups per
 namespace snmi {
 size_t bptt_workspace_bytes(const sn_bptt_desc& d);
 hipError_t bptt_forward(const sn_bptt_desc& d, const float* W, const float* x, float* counts, void* ws, hipStream_t s);
+// bptt_forward with the library's per-device scratch array as workspace; the
+// caller has checked bptt_workspace_bytes(d) <= SN_BPTT_NOALLOC_WORKSPACE_BYTES
+hipError_t bptt_forward_noalloc(const sn_bptt_desc& d, const float* W, const float* x, float* counts, hipStream_t s);
 hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, const float* dcounts, const void* ws,
                          float* dW, hipStream_t s);
 
