@@ -41,6 +41,9 @@ def _bind(lib):
     lib.or_lif_sparse.restype = ctypes.c_int
     lib.or_lif_sparse.argtypes = [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
                                   _I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int]
+    lib.or_lif_sparse_driven.restype = ctypes.c_int
+    lib.or_lif_sparse_driven.argtypes = [_I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
+                                         _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int]
     lib.or_bptt.restype = ctypes.c_int
     lib.or_bptt.argtypes = [_I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -99,6 +102,38 @@ class Oracle:
         rc = self.lib.or_lif_sparse(N, B, int(net.max_delay), T, P(th), P(lk), P(rs), P(rf), P(am),
                                     pre.shape[0], P(pre), P(post), P(w), P(d),
                                     P(ext), P(spikes), P(V), P(ref), 1)
+        if rc not in (OR_OK, OR_NONEXACT):
+            raise ValueError(f"oracle rejected the input (status {rc})")
+        return OracleResult(spikes, V, ref, rc == OR_OK)
+
+    def run_sparse_driven(self, net, history, posts=None, steps: Optional[int] = None) -> OracleResult:
+        """The update of ``net`` with source spikes taken from ``history``
+        (uint8 [B][>= T][N], e.g. the network's own raster).  With ``posts``
+        (an index array), only the synapses into those neurons are summed:
+        their columns of the result are meaningful, the others are not."""
+        T = net.steps if steps is None else int(steps)
+        ext = np.ascontiguousarray(net.ext[:, :T], dtype=np.uint8)
+        B, N = ext.shape[0], net.n
+        hist = np.ascontiguousarray(np.asarray(history)[:, :T], dtype=np.uint8)
+        assert hist.shape == (B, T, N)
+        pre, post, w, d = net.pre, net.post, net.weight, net.delay
+        if posts is not None:
+            keep = np.zeros(N, bool)
+            keep[np.asarray(posts)] = True
+            sel = keep[post]
+            pre, post, w, d = pre[sel], post[sel], w[sel], d[sel]
+        th, lk, rs, rf, am = self._params(net)
+        pre = np.ascontiguousarray(pre, dtype=np.int32)
+        post = np.ascontiguousarray(post, dtype=np.int32)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.int32)
+        spikes = np.zeros((B, T, N), np.uint8)
+        V = np.zeros((B, N), np.float64)
+        ref = np.zeros((B, N), np.int32)
+        P = self._ptr
+        rc = self.lib.or_lif_sparse_driven(N, B, int(net.max_delay), T, P(th), P(lk), P(rs), P(rf), P(am),
+                                           pre.shape[0], P(pre), P(post), P(w), P(d), P(hist),
+                                           P(ext), P(spikes), P(V), P(ref), 1)
         if rc not in (OR_OK, OR_NONEXACT):
             raise ValueError(f"oracle rejected the input (status {rc})")
         return OracleResult(spikes, V, ref, rc == OR_OK)

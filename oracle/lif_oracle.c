@@ -105,6 +105,14 @@ static int check_params(int32_t N, const double* theta, const double* leak,
  * ext and spikes are byte arrays [B][T][N] holding 0 or 1.
  * V_out [B][N] and ref_out [B][N] receive the state after step T-1.
  */
+static int lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
+                      const double* theta, const double* leak, const double* reset,
+                      const int32_t* refractory, const double* amplitude,
+                      int64_t nnz, const int32_t* pre, const int32_t* post,
+                      const double* w, const int32_t* delay,
+                      const uint8_t* history, const uint8_t* ext, uint8_t* spikes,
+                      double* V_out, int32_t* ref_out, int check_exact);
+
 int or_lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
                   const double* theta, const double* leak, const double* reset,
                   const int32_t* refractory, const double* amplitude,
@@ -112,6 +120,37 @@ int or_lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
                   const double* w, const int32_t* delay,
                   const uint8_t* ext, uint8_t* spikes,
                   double* V_out, int32_t* ref_out, int check_exact) {
+    return lif_sparse(N, B, D, T, theta, leak, reset, refractory, amplitude, nnz, pre, post, w, delay,
+                      NULL, ext, spikes, V_out, ref_out, check_exact);
+}
+
+/*
+ * The same update driven by a given spike history: step 2 takes the source
+ * spikes s_pre(t - d) from history [B][T][N] instead of the spikes computed
+ * here.  Fed the network's own raster it reproduces that raster and the final
+ * state; given only the synapses into some post-neurons, it reproduces those
+ * neurons' columns, so a large net can be checked in independent post ranges
+ * (every range checked = the whole raster, by induction over t).
+ */
+int or_lif_sparse_driven(int32_t N, int32_t B, int32_t D, int32_t T,
+                         const double* theta, const double* leak, const double* reset,
+                         const int32_t* refractory, const double* amplitude,
+                         int64_t nnz, const int32_t* pre, const int32_t* post,
+                         const double* w, const int32_t* delay,
+                         const uint8_t* history, const uint8_t* ext, uint8_t* spikes,
+                         double* V_out, int32_t* ref_out, int check_exact) {
+    if (!history) return OR_EINVAL;
+    return lif_sparse(N, B, D, T, theta, leak, reset, refractory, amplitude, nnz, pre, post, w, delay,
+                      history, ext, spikes, V_out, ref_out, check_exact);
+}
+
+static int lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
+                      const double* theta, const double* leak, const double* reset,
+                      const int32_t* refractory, const double* amplitude,
+                      int64_t nnz, const int32_t* pre, const int32_t* post,
+                      const double* w, const int32_t* delay,
+                      const uint8_t* history, const uint8_t* ext, uint8_t* spikes,
+                      double* V_out, int32_t* ref_out, int check_exact) {
     if (N < 1 || B < 1 || D < 1 || T < 0 || nnz < 0) return OR_EINVAL;
     for (int64_t k = 0; k < nnz; ++k) {
         if (pre[k] < 0 || pre[k] >= N || post[k] < 0 || post[k] >= N) return OR_EINVAL;
@@ -135,6 +174,8 @@ int or_lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
         int32_t* ref = ref_out + (size_t)b * N;
         const uint8_t* xb = ext + (size_t)b * T * N;
         uint8_t* sb = spikes + (size_t)b * T * N;
+        /* source spikes: the given history, else the spikes computed here */
+        const uint8_t* src = history ? history + (size_t)b * T * N : sb;
         for (int32_t j = 0; j < N; ++j) { V[j] = reset[j]; ref[j] = 0; }
 
         for (int32_t t = 0; t < T; ++t) {
@@ -148,7 +189,7 @@ int or_lif_sparse(int32_t N, int32_t B, int32_t D, int32_t T,
             for (int64_t k = 0; k < nnz; ++k) {
                 int32_t src_t = t - delay[k];
                 if (src_t < 0) continue;
-                if (sb[(size_t)src_t * N + pre[k]]) U[post[k]] += w[k];
+                if (src[(size_t)src_t * N + pre[k]]) U[post[k]] += w[k];
             }
             /* 3. external spikes */
             for (int32_t j = 0; j < N; ++j)

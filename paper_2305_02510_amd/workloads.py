@@ -188,6 +188,17 @@ def large_sparse(seed: int = 2, n: int = 10_000, p: float = 0.01, steps: int = 1
                    pre, post, w, d, ext)
 
 
+def large_sparse_xl(seed: int = 7, p: float = 0.01, **kw) -> Network:
+    """The largest point of the size and sparsity grid the paper benchmarks
+    (§3: ER nets of growing size and connection probability): N = 100,000 at
+    p = 0.001 (about 1e7 synapses) or p = 0.01 (about 1e8), otherwise as
+    large_sparse (weights k/64 in [-0.5, 1], delays 1..16, 5% of the neurons
+    driven Bernoulli(0.05), threshold 1, reset 0, leak 2^-4, refractory 2,
+    T = 1000)."""
+    kw.setdefault("name", f"large_sparse_xl_n100000_p{p}")
+    return large_sparse(seed, n=100_000, p=p, **kw)
+
+
 def large_sparse_low(seed: int = 2, **kw) -> Network:
     """Large sparse net with inhibition-dominated weights (k in [-64, 32]):
     firing stays low, so the event-driven push delivery is exercised."""
@@ -411,6 +422,8 @@ def by_name(name: str, seed: Optional[int] = None) -> Network:
         "large_sparse": (large_sparse, 2),
         "large_sparse_low": (large_sparse_low, 2),
         "dense_trials": (dense_trials, 3),
+        "large_sparse_xl_p0.001": (lambda seed: large_sparse_xl(seed, p=0.001), 7),
+        "large_sparse_xl_p0.01": (lambda seed: large_sparse_xl(seed, p=0.01), 7),
     }
     fn, default_seed = table[name]
     return fn(default_seed if seed is None else seed)

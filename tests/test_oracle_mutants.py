@@ -25,8 +25,8 @@ MUTANTS = {
     "delay_plus_one": ("int32_t src_t = t - delay[k];", "int32_t src_t = t - delay[k] - 1;"),
     "delay_minus_one": ("int32_t src_t = t - delay[k];", "int32_t src_t = t - delay[k] + 1;"),
     "delay_ignored": ("int32_t src_t = t - delay[k];", "int32_t src_t = t - 1;"),
-    "transposed": ("if (sb[(size_t)src_t * N + pre[k]]) U[post[k]] += w[k];",
-                   "if (sb[(size_t)src_t * N + post[k]]) U[pre[k]] += w[k];"),
+    "transposed": ("if (src[(size_t)src_t * N + pre[k]]) U[post[k]] += w[k];",
+                   "if (src[(size_t)src_t * N + post[k]]) U[pre[k]] += w[k];"),
     "unit_weight": ("U[post[k]] += w[k];", "U[post[k]] += 1.0;"),
     "external_dropped": ("U[j] += amplitude[j];", "U[j] += 0.0;"),
     "external_late": ("if (xb[(size_t)t * N + j]) U[j] += amplitude[j];",
