@@ -106,18 +106,23 @@ class Oracle:
             raise ValueError(f"oracle rejected the input (status {rc})")
         return OracleResult(spikes, V, ref, rc == OR_OK)
 
-    def run_sparse_driven(self, net, history, posts=None, steps: Optional[int] = None) -> OracleResult:
+    def run_sparse_driven(self, net, history, posts=None, steps: Optional[int] = None,
+                          syn_index=None) -> OracleResult:
         """The update of ``net`` with source spikes taken from ``history``
         (uint8 [B][>= T][N], e.g. the network's own raster).  With ``posts``
         (an index array), only the synapses into those neurons are summed:
-        their columns of the result are meaningful, the others are not."""
+        their columns of the result are meaningful, the others are not.
+        ``syn_index`` (indices into the synapse list, e.g. every synapse into
+        a post range) selects the synapses directly instead."""
         T = net.steps if steps is None else int(steps)
         ext = np.ascontiguousarray(net.ext[:, :T], dtype=np.uint8)
         B, N = ext.shape[0], net.n
         hist = np.ascontiguousarray(np.asarray(history)[:, :T], dtype=np.uint8)
         assert hist.shape == (B, T, N)
         pre, post, w, d = net.pre, net.post, net.weight, net.delay
-        if posts is not None:
+        if syn_index is not None:
+            pre, post, w, d = pre[syn_index], post[syn_index], w[syn_index], d[syn_index]
+        elif posts is not None:
             keep = np.zeros(N, bool)
             keep[np.asarray(posts)] = True
             sel = keep[post]
@@ -267,6 +272,16 @@ def host_workers() -> int:
     except AttributeError:  # pragma: no cover - non-Linux hosts
         n = os.cpu_count() or 1
     return max(1, min(16, n))
+
+
+def post_ranges(net, parts: int):
+    """Splits the neurons of ``net`` into ``parts`` contiguous post ranges and
+    returns [(j0, j1, syn_index)], syn_index = the synapses into [j0, j1)."""
+    bounds = np.linspace(0, net.n, parts + 1).astype(np.int64)
+    which = (np.searchsorted(bounds, net.post, side="right") - 1).astype(np.uint16)
+    order = np.argsort(which, kind="stable")  # a radix sort for 16-bit keys
+    cuts = np.searchsorted(which[order], np.arange(parts + 1), side="left")
+    return [(int(bounds[r]), int(bounds[r + 1]), order[cuts[r]:cuts[r + 1]]) for r in range(parts)]
 
 
 def fan_out(fn, items, workers: Optional[int] = None) -> list:

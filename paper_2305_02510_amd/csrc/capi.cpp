@@ -52,6 +52,7 @@ struct sn_net {
   void* recs = nullptr;
   void* gptr = nullptr;
   void* gsplit = nullptr;
+  void* wsec = nullptr;  // delay-phase sections of the wide per-step kernel
   // persistent-kernel plans: one slice (SMALL) and several slices (PERSIST)
   struct DevPlan {
     SlicePlan host;
@@ -687,6 +688,7 @@ sn_status sn_create_network(const sn_net_desc* desc, const sn_allocator* alloc, 
   n->d.G = G;
   n->d.B = B;
   n->d.D = D;
+  n->d.phases = 1;
   n->h_reset = rs;
 
   auto upload = [&](const void* src, size_t bytes) -> void* {
@@ -750,7 +752,19 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     if (!std::isfinite(w[k])) return fail(SN_EINVAL, "synapse %lld: weight is not finite", (long long)k);
   }
   if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
-  HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay);
+  // nets too wide for the per-group kernel's LDS history get their delay >= 2
+  // records ordered by delay phase for the wide kernel (wide.hip)
+  int32_t phase_rows = 0;
+  if (wide_net(n->d)) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, n->device) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SN_EDEVICE, "cannot query the device");
+    }
+    const WidePlan wp = wide_plan(n->d, cus);
+    if (wp.P > 1) phase_rows = wp.Dl;
+  }
+  HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows);
   if (L.too_large)
     return fail(SN_ERANGE, "%lld synapses need more than 2^31 - 1 records with the layout's fillers",
                 static_cast<long long>(nnz));
@@ -765,17 +779,18 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   void* gsplit = dev_alloc(n, L.gsplit.size() * sizeof(int32_t));
   void* orecs = dev_alloc(n, H.orecs.size() * sizeof(Rec));
   void* optr = dev_alloc(n, H.optr.size() * sizeof(int32_t));
-  bool bad = !recs || !gptr || !gsplit || !orecs || !optr;
+  void* wsec = L.phases > 1 ? dev_alloc(n, L.wsec.size() * sizeof(int32_t)) : nullptr;
+  bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec);
   void* wg_one = alloc_plan(n, one, bad);
   void* wg_many = alloc_plan(n, many, bad);
   if (bad) {
-    for (void* p : {recs, gptr, gsplit, orecs, optr, wg_one, wg_many}) dev_free(n, p);
+    for (void* p : {recs, gptr, gsplit, orecs, optr, wsec, wg_one, wg_many}) dev_free(n, p);
     return fail(SN_ENOMEM, "cannot allocate synapse records");
   }
   // the previous buffers may be in use by queued work
   SN_HIP(n, hipStreamSynchronize(n->stream));
   drop_graph(n);
-  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr}) {
+  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec}) {
     dev_free(n, *p);
     *p = nullptr;
   }
@@ -784,9 +799,13 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->gsplit = gsplit;
   n->orecs = orecs;
   n->optr = optr;
+  n->wsec = wsec;
   n->d.recs = static_cast<const Rec*>(recs);
   n->d.gptr = static_cast<const int32_t*>(gptr);
   n->d.gsplit = static_cast<const int32_t*>(gsplit);
+  n->d.wsec = static_cast<const int32_t*>(wsec);
+  n->d.phases = L.phases;
+  n->d.phase_rows = L.phase_rows;
   n->d.nnz = nnz;
   // from here on a failure is a device error, which poisons the network
   if (!L.recs.empty())
@@ -796,6 +815,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   if (!H.orecs.empty())
     SN_HIP(n, hipMemcpyAsync(orecs, H.orecs.data(), H.orecs.size() * sizeof(Rec), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipMemcpyAsync(optr, H.optr.data(), H.optr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+  if (wsec)
+    SN_HIP(n, hipMemcpyAsync(wsec, L.wsec.data(), L.wsec.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipStreamSynchronize(n->stream));  // host vectors die at return
   st = install_plan(n, n->small, one, wg_one);
   if (st != SN_OK) return st;
@@ -903,13 +924,16 @@ sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const i
     drop_graph(n);
     void* r = dev_alloc(n, static_cast<size_t>(N) * pitch);
     if (!r) return fail(SN_ENOMEM, "cannot allocate %zu bytes of dense rows", static_cast<size_t>(N) * pitch);
-    for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr}) {
+    for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec}) {
       dev_free(n, *p);
       *p = nullptr;
     }
     n->d.recs = nullptr;
     n->d.gptr = nullptr;
     n->d.gsplit = nullptr;
+    n->d.wsec = nullptr;
+    n->d.phases = 1;
+    n->d.phase_rows = 0;
     n->d.nnz = 0;
     n->small.ok = n->persist.ok = false;
     n->synapses_loaded = n->dense_loaded = false;
@@ -1284,6 +1308,7 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->recs);
   dev_free(n, n->gptr);
   dev_free(n, n->gsplit);
+  dev_free(n, n->wsec);
   dev_free(n, n->small.wg);
   dev_free(n, n->persist.wg);
   dev_free(n, n->wt);

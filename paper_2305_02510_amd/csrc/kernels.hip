@@ -1034,9 +1034,20 @@ static hipError_t launch_step_t(const DevNet& n, int32_t t, const StdpArgs& sa, 
   return hipGetLastError();
 }
 
+static hipError_t device_cus(int& cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return e;
+}
+
 hipError_t prepare_step_kernel(const DevNet& n) {
   const size_t ring = step_ring_bytes(n);
-  if (ring > kStepRingLimit) return hipSuccess;
+  if (ring > kStepRingLimit) {
+    int cus = 0;
+    const hipError_t e = device_cus(cus);
+    return e != hipSuccess ? e : prepare_wide_kernel(n, cus);
+  }
   const void* fns[] = {reinterpret_cast<const void*>(&k_step<16, 8, true, false>),
                        reinterpret_cast<const void*>(&k_step<4, 8, true, false>),
                        reinterpret_cast<const void*>(&k_step<1, 4, true, false>),
@@ -1051,6 +1062,13 @@ hipError_t prepare_step_kernel(const DevNet& n) {
 }
 
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s) {
+  if (step_ring_bytes(n) > kStepRingLimit) {
+    // the history rows do not fit one group's workgroup: workgroups of
+    // several groups stage them phase by phase (wide.hip), one per CU
+    int cus = 0;
+    const hipError_t e = device_cus(cus);
+    return e != hipSuccess ? e : launch_step_wide(n, t, cus, s);
+  }
   // enough waves per group that every lane has its U records in one pass
   const int per_group = n.G > 0 ? (static_cast<int>(n.nnz / n.G) + 1) : 1;
   const StdpArgs none{};

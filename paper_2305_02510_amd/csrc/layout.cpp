@@ -53,8 +53,13 @@ int64_t lane_rows(const std::vector<int64_t>& deg) {
 }  // namespace
 
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
-                        const uint8_t* delay) {
+                        const uint8_t* delay, int32_t max_delay, int32_t phase_rows) {
   HostLayout L;
+  // delay phases (phase p: delays p * phase_rows + 1 .. (p + 1) * phase_rows);
+  // part A holds the sections of phases P-1 .. 1, then phase 0 (delays >= 2)
+  const int32_t P = phase_rows > 0 ? std::max<int32_t>(1, (max_delay + phase_rows - 1) / phase_rows) : 1;
+  L.phases = P;
+  L.phase_rows = P > 1 ? phase_rows : 0;
   const int32_t G = (n + kGroup - 1) / kGroup;
   // bucket synapses by post-neuron, keeping input order inside a bucket
   std::vector<int64_t> colptr(static_cast<size_t>(n) + 1, 0);
@@ -75,25 +80,34 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
   };
   L.gptr.assign(static_cast<size_t>(G) + 1, 0);
   L.gsplit.assign(static_cast<size_t>(G), 0);
+  L.wsec.assign(static_cast<size_t>(G) * P, 0);
   std::vector<std::vector<int64_t>> lists(kGroup);
   std::vector<int64_t> deg(kGroup);
   for (int32_t g = 0; g < G; ++g) {
     L.gptr[g] = static_cast<int32_t>(L.recs.size());
     const int32_t j0 = g * kGroup;
     const int32_t j1 = std::min(n, j0 + kGroup);
-    for (int part = 0; part < 2; ++part) {
+    // sections: phases P-1 .. 0 of part A (delay >= 2), then part B (delay 1)
+    for (int sec = 0; sec <= P; ++sec) {
+      const int part = sec == P ? 1 : 0;
+      const int32_t ph = P - 1 - sec;  // phase of a part-A section
+      const int32_t dlo = P > 1 ? std::max(2, ph * phase_rows + 1) : 2;
+      const int32_t dhi = P > 1 ? (ph + 1) * phase_rows : 64;
       if (part == 1) L.gsplit[g] = static_cast<int32_t>(L.recs.size());
+      else L.wsec[static_cast<size_t>(g) * P + ph] = static_cast<int32_t>(L.recs.size());
       for (int l = 0; l < kGroup; ++l) {
         lists[l].clear();
         const int32_t j = j0 + l;
         if (j < j1) {
-          for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q)
-            if ((delay[order[q]] == 1) == (part == 1)) lists[l].push_back(order[q]);
+          for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+            const int32_t dq = delay[order[q]];
+            if (part == 1 ? dq == 1 : (dq >= dlo && dq <= dhi)) lists[l].push_back(order[q]);
+          }
         }
         deg[l] = static_cast<int64_t>(lists[l].size());
       }
-      // a filler names neuron 0 with a delay of this part and weight -0
-      const uint32_t fill_delay = part == 0 ? 2u : 1u;
+      // a filler names neuron 0 with a delay of this section and weight -0
+      const uint32_t fill_delay = part == 0 ? static_cast<uint32_t>(dlo) : 1u;
       const int64_t R = lane_rows(deg);
       for (int64_t r = 0; r < R; ++r) {
         for (int l = 0; l < kGroup; ++l) {

@@ -46,6 +46,14 @@ struct HostLayout {
   // set when the records with fillers would pass INT32_MAX (offsets are
   // 32-bit on the device); the other fields are then incomplete
   bool too_large = false;
+  // delay phases of the wide per-step kernel: with phase_rows > 0, part A of
+  // group g holds the sections of phases P-1 .. 1 and then phase 0 (delays
+  // >= 2), each in lane-owned rows; wsec[g * P + p] is the first record of
+  // phase p's section (phase p: delays p * phase_rows + 1 .. (p+1) * phase_rows;
+  // phase 0 runs on to the end of part B).  P = 1 without phases.
+  int32_t phases = 1;
+  int32_t phase_rows = 0;
+  std::vector<int32_t> wsec;  // [G][P]
 };
 
 
@@ -63,8 +71,10 @@ struct SlicePlan {
 // slice holding more than `max_groups` groups.  slices is clamped to [1, G].
 SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32_t max_groups);
 
+// phase_rows > 0 splits part A into delay phases of that many delays each
+// (see HostLayout), for nets of at least two phases; 0 = no phases.
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
-                        const uint8_t* delay);
+                        const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0);
 
 // Plain pointers and sizes handed to every kernel.
 struct DevNet {
@@ -90,6 +100,10 @@ struct DevNet {
   const Rec* recs;
   const int32_t* gptr;    // [G + 1]
   const int32_t* gsplit;  // [G] first delay-1 record of every group
+  // delay phases of part A (HostLayout::wsec), for the wide per-step kernel
+  const int32_t* wsec;    // [G][phases]
+  int32_t phases;         // 1: no phases
+  int32_t phase_rows;
 };
 
 // Arguments of the persistent kernel: the network plus a partition of its
@@ -234,6 +248,19 @@ int batch_blocks_per_cu(size_t lds);
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
+// Per-step kernel of nets whose D history rows do not fit in 64 KB of LDS
+// (wide.hip).  `grid` workgroups per trial own gpw groups each and stage Dl
+// history rows at a time in LDS; with P > 1 phases the layout orders part A
+// by delay phase so that every lookup is an LDS read (at most kWideMaxPhases
+// phases; otherwise P = 1 and delays above Dl read the raster in memory).
+constexpr int kWideMaxPhases = 4;
+struct WidePlan {
+  int grid = 0, gpw = 0, Dl = 0, P = 1;
+};
+bool wide_net(const DevNet& n);
+WidePlan wide_plan(const DevNet& n, int cus);
+hipError_t prepare_wide_kernel(const DevNet& n, int cus);
+hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s);
 hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_hist_build(const StdpArgs& a, int32_t t0, hipStream_t s);
 // per-step kernel with plasticity: applies the rule of step t - 1 when apply != 0

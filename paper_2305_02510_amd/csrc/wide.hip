@@ -1,0 +1,366 @@
+// Per-step pull delivery for nets whose spike history does not fit in LDS
+// (N = 100,000 with delays up to 16: 16 rows of 100,000 bits = 200 KB), the
+// synaptic input of §2.1's update summed over the pull records of every
+// post-neuron group, followed by the fused neuron update.
+//
+// One launch per step.  Workgroup (w, b) owns the contiguous groups
+// [g0, g1) of trial b.  The delays are cut into phases of Dl delays (Dl =
+// as many history rows as fit in LDS beside the sums); the layout orders the
+// delay >= 2 records of every group by phase (phases P-1 .. 1, then phase 0
+// running on into the delay-1 records).  For each phase the workgroup copies
+// the raster rows of that phase's delays into LDS once, then streams the
+// phase's records of all its groups, finding every source bit in LDS.
+// Looking each bit up in the raster in memory instead costs one scattered L2
+// request per record, which caps the record stream near 2 TB/s.  Without
+// phases (more than kWideMaxPhases would be needed) delays above Dl read the
+// raster in memory.
+//
+// Streaming: in a phase every wave walks its own records with no barrier:
+// with at least 16 groups wave w owns groups g0 + w, g0 + w + 16, ...; with
+// fewer the 16 waves are spread over the groups as teams of m (16 / ng
+// rounded up or down), member i taking batches i, i + m, ... of its group
+// (a batch is 512 records, 8 per lane).  Three record buffers
+// in rotation keep two batches in flight while one is delivered.  Lane-owned
+// rows put every record of post l in lane l, so a lane sums its post's input
+// in a register; overflow records of other posts are added into the group's
+// LDS row atomically.  An owner adds its sums into the group's row; a team's
+// members leave theirs in LDS slots that one member adds after the phase's
+// barrier.  After the last phase wave w updates groups g0 + w, g0 + w + 16,
+// ... and writes their spike words.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sn_device.h"
+#include "sn_internal.h"
+
+namespace snmi {
+
+constexpr int kWideThreads = 1024;
+constexpr int kWideWaves = kWideThreads / 64;
+constexpr int kWideU = 8;                              // records per lane in one batch
+constexpr int kWideWaveBatch = 64 * kWideU;            // records of one wave's batch
+constexpr int kWideNpw = 4;                            // groups updated per wave, at most
+constexpr int kWideStage = 8;                          // history words per thread in flight while staging
+constexpr size_t kWideStaticLds = kWideWaves * kGroup * sizeof(float) + 64;
+constexpr size_t kWideLdsLimit = 160 * 1024;
+constexpr size_t kStepRingLimitWide = 64 * 1024;  // below this the per-group kernel stages every row
+
+// Loads are unconditional, from an index clamped into [0, end) (the records
+// array always holds at least one record's worth of memory), so all of them
+// stay in flight together; records past `end` are masked when delivered.
+__device__ __forceinline__ void wide_load(const Rec* __restrict__ recs, int base, int end, int lane,
+                                          Rec (&r)[kWideU]) {
+#pragma unroll
+  for (int u = 0; u < kWideU; ++u) r[u] = recs[max(0, min(base + u * 64 + lane, end - 1))];
+}
+
+// Records of group g in phase p: phase p >= 1 is the section [wsec[p],
+// wsec[p - 1]); phase 0 runs from wsec[0] to the group's end (delay-1 part
+// included).  Without phases: all records of the group.
+__device__ __forceinline__ void wide_range(const DevNet& n, int g, int p, int& beg, int& end) {
+  if (n.phases <= 1) {
+    beg = n.gptr[g];
+    end = n.gptr[g + 1];
+    return;
+  }
+  const int32_t* ws = n.wsec + static_cast<size_t>(g) * n.phases;
+  beg = ws[p];
+  end = p == 0 ? n.gptr[g + 1] : ws[p - 1];
+}
+
+// A wave's walk over the records of one phase.  With ng >= 16 groups wave w
+// owns groups g0 + w, g0 + w + 16, ... and walks all their batches; with
+// fewer, a team of m waves shares one group, member i taking batches i,
+// i + m, ...  A batch is 512 records of one group (8 per lane).
+struct WidePair {
+  int g, k, beg, end, nb;
+  bool valid;
+};
+
+__device__ __forceinline__ void wide_enter(const DevNet& n, WidePair& s, int p) {
+  wide_range(n, s.g, p, s.beg, s.end);
+  s.nb = max(1, (s.end - s.beg + kWideWaveBatch - 1) / kWideWaveBatch);
+}
+
+__device__ __forceinline__ WidePair wide_start(const DevNet& n, int p, int g0, int g1, bool own, int team,
+                                               int member) {
+  WidePair s{};
+  s.g = g0 + team;  // own: team == wave
+  s.k = own ? 0 : member;
+  s.valid = s.g < g1;
+  if (s.valid) {
+    wide_enter(n, s, p);
+    s.valid = s.k < s.nb;
+  }
+  return s;
+}
+
+__device__ __forceinline__ WidePair wide_next(const DevNet& n, const WidePair& s, int p, int g1, int m, bool own) {
+  WidePair r = s;
+  if (!s.valid) return r;
+  r.k = s.k + m;
+  if (r.k >= s.nb) {
+    r.valid = false;
+    if (own) {  // the wave's next owned group
+      r.g = s.g + kWideWaves;
+      r.k = 0;
+      r.valid = r.g < g1;
+      if (r.valid) wide_enter(n, r, p);
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ int wide_first(const WidePair& s) { return s.beg + s.k * kWideWaveBatch; }
+
+// A pair past the wave's last one loads (and never delivers) that last
+// pair's records again.
+__device__ __forceinline__ void wide_load_pair(const Rec* __restrict__ recs, const WidePair& s, int lane,
+                                               Rec (&r)[kWideU]) {
+  wide_load(recs, wide_first(s), s.end, lane, r);
+}
+
+// FALLBACK: no delay phases and more delays than staged rows; delays above
+// the staged rows read the raster in memory.
+// NPW: groups one wave updates at most (1 when a workgroup has <= 16).
+template <bool FALLBACK, int NPW>
+__global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int t, int Dl, int P) {
+  extern __shared__ __align__(16) uint32_t smem[];
+  __shared__ float part[kWideWaves][kGroup];
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int W32 = 2 * n.G;
+  const size_t rstride = static_cast<size_t>(n.B) * n.G;
+  const uint64_t* hist = n.raster + static_cast<size_t>(b) * n.G;
+  const int g0 = static_cast<int>(static_cast<int64_t>(n.G) * blockIdx.x / gridDim.x);
+  const int g1 = static_cast<int>(static_cast<int64_t>(n.G) * (blockIdx.x + 1) / gridDim.x);
+  const int ng = g1 - g0;
+  // with fewer groups than waves, group q gets waves ceil(16q/ng) ..
+  // ceil(16(q+1)/ng) - 1 (2 or 3 waves for 7 groups); else every wave owns
+  const bool own = ng >= kWideWaves;
+  const int team = own ? wave : wave * ng / kWideWaves;
+  const int tfirst = own ? wave : (team * kWideWaves + ng - 1) / ng;
+  const int m = own ? 1 : (team + 1 == ng ? kWideWaves : ((team + 1) * kWideWaves + ng - 1) / ng) - tfirst;
+  const int member = wave - tfirst;
+  uint32_t* ring = smem;                                              // [Dl][W32]
+  float* gacc = reinterpret_cast<float*>(smem + static_cast<size_t>(Dl) * W32);  // [g1 - g0][64]
+
+  // neuron state of the groups this wave updates, loaded now, used last
+  float V[NPW], th[NPW], lam[NPW], rs[NPW], amp[NPW];
+  int ref[NPW], R[NPW];
+  uint64_t ew[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int g = g0 + wave + i * kWideWaves;
+    V[i] = th[i] = lam[i] = rs[i] = amp[i] = 0.f;
+    ref[i] = R[i] = 0;
+    ew[i] = 0;
+    if (g < g1) {
+      const int j = g * kGroup + lane;
+      const size_t sj = static_cast<size_t>(b) * n.Npad + j;
+      V[i] = n.V[sj];
+      ref[i] = n.ref[sj];
+      th[i] = n.theta[j];
+      lam[i] = n.leak[j];
+      rs[i] = n.reset[j];
+      amp[i] = n.amp[j];
+      R[i] = n.refr[j];
+      ew[i] = n.ext[row_word(n, t, b, g)];
+    }
+  }
+  for (int i = tid; i < (g1 - g0) * kGroup; i += kWideThreads) gacc[i] = 0.f;
+
+  for (int p = 0; p < P; ++p) {
+    const int dbase = p * Dl;  // the phase's delays are dbase + 1 .. dbase + Dl
+    const int rows = min(Dl, n.D - dbase);
+    // stage the phase's rows: every load of a round is issued before its
+    // stores, so a round costs one memory latency, not one per word
+    for (int base = 0; base < rows * n.G; base += kWideThreads * kWideStage) {
+      uint64_t v[kWideStage];
+#pragma unroll
+      for (int q = 0; q < kWideStage; ++q) {
+        const int i = base + q * kWideThreads + tid;
+        const int r = i / n.G, w = i - r * n.G;
+        const int ts = t - (dbase + r + 1);
+        v[q] = (i < rows * n.G && ts >= 0) ? hist[static_cast<size_t>(ts) * rstride + w] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < kWideStage; ++q) {
+        const int i = base + q * kWideThreads + tid;
+        if (i < rows * n.G) {
+          const int r = i / n.G, w = i - r * n.G;
+          ring[r * W32 + 2 * w] = static_cast<uint32_t>(v[q]);
+          ring[r * W32 + 2 * w + 1] = static_cast<uint32_t>(v[q] >> 32);
+        }
+      }
+    }
+    __syncthreads();
+
+    // this wave's (group, batch) walk: no barrier until the phase ends, three
+    // record buffers in rotation keep two batches in flight while one is
+    // delivered (no buffer is copied: a copy would wait for its load)
+    WidePair s0 = wide_start(n, p, g0, g1, own, team, member);
+    WidePair s1 = wide_next(n, s0, p, g1, m, own), s2 = wide_next(n, s1, p, g1, m, own);
+    Rec b0[kWideU], b1[kWideU], b2[kWideU];
+    wide_load_pair(n.recs, s0, lane, b0);
+    wide_load_pair(n.recs, s1, lane, b1);
+    wide_load_pair(n.recs, s2, lane, b2);
+    float sum = 0.f;
+    // delivers the batch of pair sc; an owned group's sum is added to its row
+    // when the walk leaves it; false when sc was the wave's last pair
+    auto body = [&](const WidePair& sc, const Rec (&cur)[kWideU], const WidePair& sn) -> bool {
+      if (!sc.valid) return false;
+      float* acc_g = gacc + (sc.g - g0) * kGroup;
+      const int first = wide_first(sc) + lane;
+      uint32_t bit[kWideU];
+#pragma unroll
+      for (int u = 0; u < kWideU; ++u) {
+        const uint32_t mt = cur[u].meta;
+        const int d = static_cast<int>((mt >> 20) & 63u) + 1;
+        const uint32_t pre = mt & 0xFFFFFu;
+        const bool valid = first + u * 64 < sc.end;
+        const int r = d - dbase - 1;  // row of the phase's staged rows
+        if (!FALLBACK) {
+          // every record of the phase lies in its rows; a masked one may not
+          const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), rows - 1));
+          bit[u] = (ring[__umul24(rc, static_cast<uint32_t>(W32)) + (pre >> 5)] >> (pre & 31u)) &
+                   static_cast<uint32_t>(valid);
+        } else if (r < rows) {
+          bit[u] = (ring[__umul24(static_cast<uint32_t>(r), static_cast<uint32_t>(W32)) + (pre >> 5)] >> (pre & 31u)) &
+                   static_cast<uint32_t>(valid);
+        } else {  // a delay beyond the staged rows
+          bit[u] = valid && t - d >= 0
+                       ? static_cast<uint32_t>(hist[static_cast<size_t>(t - d) * rstride + (pre >> 6)] >> (pre & 63u)) & 1u
+                       : 0u;
+        }
+      }
+      bool other = false;  // an active overflow record of another lane's post
+#pragma unroll
+      for (int u = 0; u < kWideU; ++u) {
+        const uint32_t post = cur[u].meta >> 26;
+        sum += (bit[u] && post == static_cast<uint32_t>(lane)) ? cur[u].w : 0.f;
+        other |= bit[u] && post != static_cast<uint32_t>(lane);
+      }
+      if (other) {  // rare: overflow records follow the lane-owned rows
+#pragma unroll
+        for (int u = 0; u < kWideU; ++u) {
+          const uint32_t post = cur[u].meta >> 26;
+          if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], cur[u].w);
+        }
+      }
+      if (own && (!sn.valid || sn.g != sc.g)) {  // an owned group: this wave is its only contributor
+        acc_g[lane] += sum;
+        sum = 0.f;
+      }
+      return sn.valid;
+    };
+    for (;;) {
+      if (!body(s0, b0, s1)) break;
+      const WidePair s3 = wide_next(n, s2, p, g1, m, own);
+      wide_load_pair(n.recs, s3, lane, b0);
+      if (!body(s1, b1, s2)) break;
+      const WidePair s4 = wide_next(n, s3, p, g1, m, own);
+      wide_load_pair(n.recs, s4, lane, b1);
+      if (!body(s2, b2, s3)) break;
+      const WidePair s5 = wide_next(n, s4, p, g1, m, own);
+      wide_load_pair(n.recs, s5, lane, b2);
+      s0 = s3;
+      s1 = s4;
+      s2 = s5;
+    }
+    if (!own) {  // a team of m waves per group: the sums meet in LDS
+      part[wave][lane] = sum;
+      __syncthreads();
+      if (member == 0) {
+        float a = gacc[team * kGroup + lane];
+        for (int i = 0; i < m; ++i) a += part[tfirst + i][lane];
+        gacc[team * kGroup + lane] = a;
+      }
+    }
+    __syncthreads();  // every lookup of this phase done, every group row complete
+  }
+
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int g = g0 + wave + i * kWideWaves;
+    if (g < g1) {  // uniform per wave
+      const float syn = gacc[(g - g0) * kGroup + lane];
+      const bool s = lif_update(V[i], ref[i], syn, (ew[i] >> lane) & 1ull, th[i], lam[i], rs[i], amp[i], R[i]);
+      const uint64_t sw = __ballot(s);
+      const int j = g * kGroup + lane;
+      const size_t sj = static_cast<size_t>(b) * n.Npad + j;
+      n.V[sj] = V[i];
+      n.ref[sj] = static_cast<uint8_t>(ref[i]);
+      if (lane == 0) n.raster[row_word(n, t, b, g)] = sw;
+    }
+  }
+}
+
+bool wide_net(const DevNet& n) {
+  return static_cast<size_t>(n.D) * 2 * n.G * sizeof(uint32_t) > kStepRingLimitWide;
+}
+
+WidePlan wide_plan(const DevNet& n, int cus) {
+  WidePlan w;
+  w.grid = std::max(1, std::min(cus, n.G));
+  w.gpw = (n.G + w.grid - 1) / w.grid;
+  if (w.gpw > kWideNpw * kWideWaves) {  // more groups than the waves can update: more workgroups
+    w.gpw = kWideNpw * kWideWaves;
+    w.grid = (n.G + w.gpw - 1) / w.gpw;
+  }
+  const size_t row = static_cast<size_t>(2 * n.G) * sizeof(uint32_t);
+  const size_t sums = static_cast<size_t>(w.gpw) * kGroup * sizeof(float);
+  const size_t avail = kWideLdsLimit - kWideStaticLds - sums;
+  w.Dl = static_cast<int>(std::min<size_t>(avail / row, static_cast<size_t>(n.D)));
+  w.P = w.Dl > 0 ? (n.D + w.Dl - 1) / w.Dl : 0;
+  if (w.P > kWideMaxPhases) w.P = 1;  // too many phases: delays above Dl read memory
+  return w;
+}
+
+static size_t wide_lds(const DevNet& n, const WidePlan& w, int Dl) {
+  return static_cast<size_t>(Dl) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(w.gpw) * kGroup * sizeof(float);
+}
+
+// Phases come from the layout (n.phases, n.phase_rows); a layout without
+// phases runs with as many rows as fit.
+static int wide_rows_of(const DevNet& n, const WidePlan& w) { return n.phases > 1 ? n.phase_rows : w.Dl; }
+
+hipError_t prepare_wide_kernel(const DevNet& n, int cus) {
+  const WidePlan w = wide_plan(n, cus);
+  const int Dl = wide_rows_of(n, w);
+  if (Dl < 1 || wide_lds(n, w, Dl) + kWideStaticLds > kWideLdsLimit) return hipErrorInvalidValue;
+  const int bytes = static_cast<int>(wide_lds(n, w, Dl));
+  const void* fns[] = {reinterpret_cast<const void*>(&k_step_wide<false, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) {
+  const WidePlan w = wide_plan(n, cus);
+  const int Dl = wide_rows_of(n, w);
+  const int P = n.phases > 1 ? n.phases : 1;
+  if (Dl < 1 || wide_lds(n, w, Dl) + kWideStaticLds > kWideLdsLimit) return hipErrorInvalidValue;
+  if (P > 1 && Dl * P < n.D) return hipErrorInvalidValue;  // phases must cover every delay
+  const bool fallback = P == 1 && Dl < n.D;
+  const dim3 grid(w.grid, n.B), block(kWideThreads);
+  const size_t lds = wide_lds(n, w, Dl);
+  if (w.gpw <= kWideWaves) {
+    if (fallback) hipLaunchKernelGGL((k_step_wide<true, 1>), grid, block, lds, s, n, t, Dl, P);
+    else hipLaunchKernelGGL((k_step_wide<false, 1>), grid, block, lds, s, n, t, Dl, P);
+  } else {
+    if (fallback) hipLaunchKernelGGL((k_step_wide<true, kWideNpw>), grid, block, lds, s, n, t, Dl, P);
+    else hipLaunchKernelGGL((k_step_wide<false, kWideNpw>), grid, block, lds, s, n, t, Dl, P);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace snmi

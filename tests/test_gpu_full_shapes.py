@@ -136,3 +136,34 @@ def test_rows_beyond_2gib_every_column(gpu, oracle):
 
     bad = [c0 for c0, ok in om.fan_out(columns, range(0, n, chunk)) if not ok]
     assert not bad, f"columns starting at {bad[:8]} differ from the oracle"
+
+
+@pytest.mark.parametrize("p", [0.001, 0.01])
+def test_sparse_xl_every_post_range(gpu, oracle, p):
+    """N = 100,000 sparse nets (1e7 and 1e8 synapses, records far beyond
+    LDS), on the path the autotuner picks; every post range recomputed by the
+    history-driven oracle from the GPU raster (all ranges = whole-network
+    parity, by induction over t)."""
+    import oracle as om
+    steps = 200
+    net = wl.large_sparse_xl(p=p, steps=steps)
+    print(f"sparse xl: N={net.n} p={p} nnz={net.nnz} T={steps}", flush=True)
+    g = gpu.from_workload(net)
+    path, slices = g.autotune(64)
+    g.run(steps)
+    assert g.progress[1] == path
+    s = g.read_raster(0, steps)
+    V, ref = g.read_state()
+    g.close()
+    print(f"sparse xl: path {path}/{slices}, rate {s.mean():.4f}", flush=True)
+    assert 0.05 < s.mean() < 0.5
+
+    def check(rng):
+        j0, j1, idx = rng
+        res = oracle.run_sparse_driven(net, s, syn_index=idx)
+        return (res.exact and np.array_equal(s[:, :, j0:j1], res.spikes[:, :, j0:j1])
+                and np.array_equal(V[:, j0:j1].astype(np.float64), res.V[:, j0:j1])
+                and np.array_equal(ref[:, j0:j1].astype(np.int32), res.ref[:, j0:j1])), j0
+    ranges = om.post_ranges(net, 4 * om.host_workers())
+    bad = [j0 for ok, j0 in om.fan_out(check, ranges) if not ok]
+    assert not bad, f"post ranges starting at {bad[:8]} differ from the oracle ({path})"

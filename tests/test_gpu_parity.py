@@ -162,6 +162,34 @@ def test_persist_global_ring(gpu, oracle):
         assert_parity(net, res, s, V, r, f"{path} slices={slices}")
 
 
+def _with_hubs(net, seed, hubs=3, extra=1500):
+    """The same net with `extra` more synapses into each of `hubs` posts
+    (overflow records beyond the lane-owned rows), all delays."""
+    rng = np.random.default_rng(seed)
+    posts = rng.choice(net.n, hubs, replace=False)
+    pre = np.concatenate([net.pre] + [rng.choice(net.n, extra).astype(np.int32) for _ in posts])
+    post = np.concatenate([net.post] + [np.full(extra, j, np.int32) for j in posts])
+    w = np.concatenate([net.weight, (rng.integers(-8, 9, hubs * extra) / 64).astype(np.float32)])
+    d = np.concatenate([net.delay, rng.integers(1, net.max_delay + 1, hubs * extra).astype(np.uint8)])
+    return dataclasses.replace(net, pre=pre, post=post, weight=w, delay=d, name=net.name + "_hubs")
+
+
+@pytest.mark.parametrize("n,p,D,trials", [(20_000, 0.002, 64, 2), (33_000, 0.001, 20, 1), (70_000, 0.0004, 40, 1)])
+def test_wide_step_delay_phases(gpu, oracle, n, p, D, trials):
+    """Per-step path of nets whose history rows exceed the per-group kernel's
+    LDS: workgroups of several groups deliver the records phase by phase of
+    delays (history rows staged per phase), hub posts with overflow records,
+    several trials, resumed runs."""
+    net = wl.large_sparse(40 + D, n=n, p=p, steps=90, max_delay=D)
+    net = _with_hubs(dataclasses.replace(net, trials=trials, ext=np.concatenate([net.ext] * trials)), 7 + D)
+    if trials > 1:  # different inputs per trial
+        net.ext[1] = np.roll(net.ext[1], 3, axis=0)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "step", chunks=[1, 40, 49])
+    assert used == "step"
+    assert_parity(net, res, s, V, r, f"wide step n={n} D={D} trials={trials}")
+
+
 def test_large_sparse_low_rate(gpu, oracle):
     net = wl.large_sparse_low(2, steps=300)
     res = oracle.run_sparse(net)
