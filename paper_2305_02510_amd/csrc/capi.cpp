@@ -53,6 +53,7 @@ struct sn_net {
   void* gptr = nullptr;
   void* gsplit = nullptr;
   void* wsec = nullptr;  // delay-phase sections of the wide per-step kernel
+  void* crecs = nullptr; // 4-byte record copies (compact_records), when the net allows them
   // persistent-kernel plans: one slice (SMALL) and several slices (PERSIST)
   struct DevPlan {
     SlicePlan host;
@@ -452,7 +453,9 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
   // (its spike ring, accumulators, partial sums and group offsets)
   size_t lds = 0;
   for (sn_net* n : v) lds = std::max(lds, batch_lds_bytes(n->d, std::min<int32_t>(n->d.G, kBatchMaxGroups)));
-  const int per_cu = batch_blocks_per_cu(lds);
+  // the grid must fit either kernel variant (a net reloaded later may lose
+  // its compact records)
+  const int per_cu = std::min(batch_blocks_per_cu(lds, false), batch_blocks_per_cu(lds, true));
   if (per_cu < 1) {
     delete bt;
     return fail(SN_ERANGE, "batch kernel does not fit on a compute unit");
@@ -592,7 +595,9 @@ sn_status sn_batch_run(sn_batch* bt, int32_t n_steps) {
   ba.n_team = static_cast<int32_t>(bt->team.size());
   ba.n_queue = static_cast<int32_t>(bt->queue.size());
   ba.queue_head = static_cast<int32_t*>(bt->head_buf);
-  e = launch_batch(ba, bt->grid, bt->lds, n_steps, bt->stream);
+  bool compact = true;
+  for (sn_net* n : bt->nets) compact = compact && n->d.crecs != nullptr;
+  e = launch_batch(ba, bt->grid, bt->lds, n_steps, compact, bt->stream);
   if (e != hipSuccess) return poison(e, "batch launch");
   for (sn_net* n : bt->nets) {
     n->t += n_steps;
@@ -769,6 +774,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     return fail(SN_ERANGE, "%lld synapses need more than 2^31 - 1 records with the layout's fillers",
                 static_cast<long long>(nnz));
   HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
+  float cscale = 0.f;
+  const std::vector<uint32_t> C = compact_records(L, n->d.N, n->d.D, &cscale);
   SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
   if (!fit_plan(n->d, one)) one.P = 0;
   SlicePlan many = plan_persist(n->d, L, n->slices_req);
@@ -780,17 +787,18 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   void* orecs = dev_alloc(n, H.orecs.size() * sizeof(Rec));
   void* optr = dev_alloc(n, H.optr.size() * sizeof(int32_t));
   void* wsec = L.phases > 1 ? dev_alloc(n, L.wsec.size() * sizeof(int32_t)) : nullptr;
-  bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec);
+  void* crecs = C.empty() ? nullptr : dev_alloc(n, C.size() * sizeof(uint32_t));
+  bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec) || (!C.empty() && !crecs);
   void* wg_one = alloc_plan(n, one, bad);
   void* wg_many = alloc_plan(n, many, bad);
   if (bad) {
-    for (void* p : {recs, gptr, gsplit, orecs, optr, wsec, wg_one, wg_many}) dev_free(n, p);
+    for (void* p : {recs, gptr, gsplit, orecs, optr, wsec, crecs, wg_one, wg_many}) dev_free(n, p);
     return fail(SN_ENOMEM, "cannot allocate synapse records");
   }
   // the previous buffers may be in use by queued work
   SN_HIP(n, hipStreamSynchronize(n->stream));
   drop_graph(n);
-  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec}) {
+  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec, &n->crecs}) {
     dev_free(n, *p);
     *p = nullptr;
   }
@@ -800,6 +808,9 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->orecs = orecs;
   n->optr = optr;
   n->wsec = wsec;
+  n->crecs = crecs;
+  n->d.crecs = static_cast<const uint32_t*>(crecs);
+  n->d.cscale = cscale;
   n->d.recs = static_cast<const Rec*>(recs);
   n->d.gptr = static_cast<const int32_t*>(gptr);
   n->d.gsplit = static_cast<const int32_t*>(gsplit);
@@ -817,6 +828,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   SN_HIP(n, hipMemcpyAsync(optr, H.optr.data(), H.optr.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   if (wsec)
     SN_HIP(n, hipMemcpyAsync(wsec, L.wsec.data(), L.wsec.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+  if (crecs)
+    SN_HIP(n, hipMemcpyAsync(crecs, C.data(), C.size() * sizeof(uint32_t), hipMemcpyHostToDevice, n->stream));
   SN_HIP(n, hipStreamSynchronize(n->stream));  // host vectors die at return
   st = install_plan(n, n->small, one, wg_one);
   if (st != SN_OK) return st;
@@ -924,10 +937,12 @@ sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const i
     drop_graph(n);
     void* r = dev_alloc(n, static_cast<size_t>(N) * pitch);
     if (!r) return fail(SN_ENOMEM, "cannot allocate %zu bytes of dense rows", static_cast<size_t>(N) * pitch);
-    for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec}) {
+    for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec,
+                     &n->crecs}) {
       dev_free(n, *p);
       *p = nullptr;
     }
+    n->d.crecs = nullptr;
     n->d.recs = nullptr;
     n->d.gptr = nullptr;
     n->d.gsplit = nullptr;
@@ -1309,6 +1324,7 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->gptr);
   dev_free(n, n->gsplit);
   dev_free(n, n->wsec);
+  dev_free(n, n->crecs);
   dev_free(n, n->small.wg);
   dev_free(n, n->persist.wg);
   dev_free(n, n->wt);

@@ -71,20 +71,49 @@ __host__ __device__ __forceinline__ int acc_rows(int ng_max, int nwave) {
 }
 
 // Records [k, k + 4 * 64) of the calling lane's chunk (four, 64 apart);
-// valid[u] is false past `end`.  LDS loads are issued unconditionally with
-// the index clamped into the chunk, so the four are in flight together.
-template <bool RECS_LDS>
+// valid[u] is false past `end`.  Loads are issued unconditionally with the
+// index clamped into the chunk (start < end), so the four are in flight
+// together; deliver_chunk masks the invalid ones.  COMPACT reads the 4-byte
+// copies of the records (n.crecs) and expands them to weight and meta word.
+// A record as held between its load and its delivery: the 8-byte record,
+// or with COMPACT its 4-byte copy, expanded only when delivered (a chunk in
+// flight then costs half the registers).
+template <bool COMPACT>
+struct RecHeld {
+  using type = Rec;
+};
+template <>
+struct RecHeld<true> {
+  using type = uint32_t;
+};
+
+template <bool RECS_LDS, bool COMPACT = false>
 __device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int start, int end, int lane, int r0,
-                                          Rec (&rc)[4], bool (&valid)[4]) {
+                                          typename RecHeld<COMPACT>::type (&rc)[4], bool (&valid)[4]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int k = start + lane + 64 * u;
     valid[u] = k < end;
-    if (RECS_LDS) {
-      rc[u] = lrec[(k < end ? k : start) - r0];
+    const int kc = k < end ? k : end - 1;
+    if constexpr (COMPACT) {
+      rc[u] = n.crecs[kc];
+    } else if constexpr (RECS_LDS) {
+      rc[u] = lrec[kc - r0];
     } else {
-      rc[u] = Rec{0.f, 0u};
-      if (k < end) rc[u] = n.recs[k];
+      rc[u] = n.recs[kc];
+    }
+  }
+}
+
+template <bool COMPACT>
+__device__ __forceinline__ void expand_recs(const DevNet& n, const typename RecHeld<COMPACT>::type (&held)[4],
+                                            Rec (&rc)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if constexpr (COMPACT) {
+      rc[u] = expand_compact(held[u], n.cscale);
+    } else {
+      rc[u] = held[u];
     }
   }
 }
@@ -148,7 +177,7 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[4
 
 // Slot mode: the chunks member, member + m, ... of the records [beg, end)
 // of one group part.  Returns the lane's own-post sum.
-template <bool RECS_LDS, bool RING_LDS>
+template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false>
 __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec, const uint32_t* ring,
                                                const uint64_t* mring, float* acc_g, int beg, int end, int member,
                                                int m, int lane, int r0, int t, int cur, int Dr, int W32) {
@@ -158,17 +187,20 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
   const uint32_t curW = static_cast<uint32_t>(cur * W32);
   const uint32_t DrW = static_cast<uint32_t>(Dr * W32);
   const int stride = m * kChunk;
-  Rec rc[4];
+  using Held = typename RecHeld<COMPACT>::type;
+  Held rc[4];
   bool valid[4];
-  load_recs<RECS_LDS>(n, lrec, start, end, lane, r0, rc, valid);
+  load_recs<RECS_LDS, COMPACT>(n, lrec, start, end, lane, r0, rc, valid);
   for (; start < end; start += stride) {
-    Rec nx[4];
+    Held nx[4];
     bool nvalid[4];
-    if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
-    deliver_chunk<RECS_LDS, RING_LDS>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS, COMPACT>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
+    Rec ex[4];
+    expand_recs<COMPACT>(n, rc, ex);
+    deliver_chunk<RECS_LDS, RING_LDS>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
     if (start + stride < end) {
       if (RECS_LDS) {
-        load_recs<RECS_LDS>(n, lrec, start + stride, end, lane, r0, rc, valid);
+        load_recs<RECS_LDS, COMPACT>(n, lrec, start + stride, end, lane, r0, rc, valid);
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -191,7 +223,7 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
 // (Range: atomically unless the whole group lies in [lo, hi)).  Records of
 // other posts (overflow) are added into acc[lg][post] atomically.  Records
 // in global memory are prefetched one chunk ahead, across group changes.
-template <bool RECS_LDS, bool RING_LDS>
+template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false>
 __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const uint32_t* ring,
                                          const uint64_t* mring, float* acc, const int* cs, const int* bp,
                                          const int* ep, int ng, int lg, int c, int cstride, int gstep, int lo, int hi,
@@ -210,9 +242,10 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
   // the current group's records, first chunk and chunk bound (re-read from
   // LDS only when the walk moves to another group)
   int beg = bp[lg], end = ep[lg], c0 = cs[lg], cend = item_end(lg);
-  Rec rc[4];
+  using Held = typename RecHeld<COMPACT>::type;
+  Held rc[4];
   bool valid[4];
-  load_recs<RECS_LDS>(n, lrec, beg + (c - c0) * kChunk, end, lane, r0, rc, valid);
+  load_recs<RECS_LDS, COMPACT>(n, lrec, beg + (c - c0) * kChunk, end, lane, r0, rc, valid);
   float sum = 0.f;
   for (;;) {
     // the next item
@@ -239,11 +272,13 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
       nc0 = cs[nlg];
       ncend = item_end(nlg);
     }
-    Rec nx[4];
+    Held nx[4];
     bool nvalid[4];
-    if (!RECS_LDS && more) load_recs<RECS_LDS>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, nx, nvalid);
+    if (!RECS_LDS && more) load_recs<RECS_LDS, COMPACT>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, nx, nvalid);
     float* acc_g = acc + lg * kGroup;
-    deliver_chunk<RECS_LDS, RING_LDS>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    Rec ex[4];
+    expand_recs<COMPACT>(n, rc, ex);
+    deliver_chunk<RECS_LDS, RING_LDS>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
     if (!more || nlg != lg) {  // flush the group's register sum (uniform)
       if (mode == kModeSlot) {
         ret = sum;
@@ -256,7 +291,7 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
     }
     if (!more) break;
     if (RECS_LDS) {
-      load_recs<RECS_LDS>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, rc, valid);
+      load_recs<RECS_LDS, COMPACT>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, rc, valid);
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -276,7 +311,7 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
 
 // PARAMS_LDS: neuron parameters live in LDS instead of registers (the batch
 // kernel, whose occupancy is bound by registers, not LDS).
-template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI, bool PARAMS_LDS = false>
+template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI, bool PARAMS_LDS = false, bool COMPACT = false>
 __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0, int steps, unsigned char* smem,
                                          int& abort_flag) {
   const DevNet& n = a.n;
@@ -436,10 +471,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     float sum = 0.f;
     if (mode == kModeSlot) {  // uniform per wave
       if (team < ng)
-        sum = deliver_group<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb + team * kGroup, gsp[team],
+        sum = deliver_group<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb + team * kGroup, gsp[team],
                                                 gsp[ng + 1 + team], member, m, lane, r0, t, cur, Dr, W32);
     } else if (wlg[0] < ng) {
-      deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb, csA, gsp, gsp + ng + 1, ng, wlg[0], wc[0], cstride,
+      deliver<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb, csA, gsp, gsp + ng + 1, ng, wlg[0], wc[0], cstride,
                                   gstep, wlo[0], whi[0], mode, lane, r0, t, cur, Dr, W32);
     }
     if (receive) {
@@ -464,10 +499,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     // delay 1
     if (mode == kModeSlot) {
       if (team < ng)
-        sum += deliver_group<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb + team * kGroup, gsp[ng + 1 + team],
+        sum += deliver_group<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb + team * kGroup, gsp[ng + 1 + team],
                                                  gsp[team + 1], member, m, lane, r0, t, cur, Dr, W32);
     } else if (wlg[1] < ng) {
-      deliver<RECS_LDS, RING_LDS>(n, lrec, ring, mring, accb, csB, gsp + ng + 1, gsp + 1, ng, wlg[1], wc[1], cstride,
+      deliver<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb, csB, gsp + ng + 1, gsp + 1, ng, wlg[1], wc[1], cstride,
                                   gstep, wlo[1], whi[1], mode, lane, r0, t, cur, Dr, W32);
     }
     if (mode == kModeSlot) part[wave * kGroup + lane] = sum;  // partial sums for the updating wave
@@ -565,6 +600,8 @@ hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
 // queue is empty.  Team slices wait only on slices of the same network, all
 // of which are resident (cooperative launch) and start with their team task.
 // ---------------------------------------------------------------------------
+// COMPACT: every network of the batch has 4-byte record copies (n.crecs).
+template <bool COMPACT>
 __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, int steps) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int abort_flag;
@@ -572,7 +609,7 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, 
   if (static_cast<int>(blockIdx.x) < ba.n_team) {
     const int4 tt = ba.team[blockIdx.x];
     const SimArgs a = ba.nets[tt.x].team;
-    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true, true>(a, tt.y, tt.z, tt.w, steps, smem,
+    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true, true, COMPACT>(a, tt.y, tt.z, tt.w, steps, smem,
                                                                                    abort_flag))
       return;
   }
@@ -584,7 +621,7 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, 
     if (i >= ba.n_queue) return;
     const int4 qt = ba.queue[i];
     const SimArgs a = ba.nets[qt.x].single;
-    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false, true>(a, 0, qt.y, qt.z, steps, smem,
+    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false, true, COMPACT>(a, 0, qt.y, qt.z, steps, smem,
                                                                                abort_flag);
   }
 }
@@ -607,17 +644,18 @@ size_t batch_lds_bytes(const DevNet& n, int ng_max) {
          static_cast<size_t>(5) * ng_max * kGroup * sizeof(float);
 }
 
-int batch_blocks_per_cu(size_t lds) {
+int batch_blocks_per_cu(size_t lds, bool compact) {
   int blocks = 0;
-  const void* fn = reinterpret_cast<const void*>(&k_batch);
+  const void* fn = compact ? reinterpret_cast<const void*>(&k_batch<true>) : reinterpret_cast<const void*>(&k_batch<false>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch, kBatchThreads, lds) != hipSuccess) return 0;
-  return blocks;
+  const hipError_t e = compact ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<true>, kBatchThreads, lds)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<false>, kBatchThreads, lds);
+  return e == hipSuccess ? blocks : 0;
 }
 
-hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s) {
-  const void* fn = reinterpret_cast<const void*>(&k_batch);
+hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, bool compact, hipStream_t s) {
+  const void* fn = compact ? reinterpret_cast<const void*>(&k_batch<true>) : reinterpret_cast<const void*>(&k_batch<false>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
   void* args[] = {const_cast<BatchArgs*>(&a), &steps};

@@ -145,6 +145,24 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
   return L;
 }
 
+std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t max_delay, float* scale) {
+  std::vector<uint32_t> out;
+  if (n > kCompactMaxNeurons || max_delay > kCompactMaxDelay || L.recs.empty()) return out;
+  std::vector<float> w(L.recs.size());
+  for (size_t i = 0; i < w.size(); ++i) w[i] = L.recs[i].w;
+  const int32_t e = int8_exponent(w.data(), static_cast<int64_t>(w.size()));
+  if (e < 0) return out;
+  const float f = std::ldexp(1.f, e);
+  out.resize(L.recs.size());
+  for (size_t i = 0; i < out.size(); ++i) {
+    const Rec& r = L.recs[i];
+    const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
+    out[i] = compact_record(k, r.meta & 0xFFFFFu, ((r.meta >> 20) & 63u) + 1u, r.meta >> 26);
+  }
+  *scale = std::ldexp(1.f, -e);
+  return out;
+}
+
 // Greedy contiguous split with a record cap; returns the number of slices.
 static int32_t greedy_slices(const HostLayout& L, int32_t G, int64_t cap, int32_t max_groups,
                              std::vector<int32_t>* starts) {

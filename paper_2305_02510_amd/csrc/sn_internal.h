@@ -104,7 +104,24 @@ struct DevNet {
   const int32_t* wsec;    // [G][phases]
   int32_t phases;         // 1: no phases
   int32_t phase_rows;
+  // 4-byte copies of the records (same order), or null: see compact_record
+  const uint32_t* crecs;
+  float cscale;           // 2^-e: weight = (int8 numerator) * cscale
 };
+
+// Compact record, 4 bytes, for nets with N <= 16384, delays <= 16 and every
+// weight k * 2^-e with |k| <= 127:
+//   bits  0..7   k (int8)      bits  8..11  delay - 1
+//   bits 12..17  post within its group      bits 18..31  pre-neuron
+constexpr int32_t kCompactMaxNeurons = 1 << 14;
+constexpr int32_t kCompactMaxDelay = 16;
+__host__ __device__ inline uint32_t compact_record(int32_t k, uint32_t pre, uint32_t delay, uint32_t post_local) {
+  return (static_cast<uint32_t>(k) & 0xFFu) | ((delay - 1u) << 8) | (post_local << 12) | (pre << 18);
+}
+__host__ __device__ inline Rec expand_compact(uint32_t c, float scale) {
+  const float w = static_cast<float>(static_cast<int8_t>(c & 0xFFu)) * scale;
+  return Rec{w, (c >> 18) | (((c >> 8) & 15u) << 20) | (((c >> 12) & 63u) << 26)};
+}
 
 // Arguments of the persistent kernel: the network plus a partition of its
 // post-neuron groups into P slices (one workgroup per slice and trial).
@@ -244,9 +261,12 @@ int sim_npt(int ng_max, int64_t max_recs);
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s);
 hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s);
 size_t batch_lds_bytes(const DevNet& n, int ng_max);
-int batch_blocks_per_cu(size_t lds);
+int batch_blocks_per_cu(size_t lds, bool compact);
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
-hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, hipStream_t s);
+hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, bool compact, hipStream_t s);
+// 4-byte copies of the layout's records (compact_record), or empty when the
+// net or a weight does not allow them; *scale receives 2^-e.
+std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t max_delay, float* scale);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
 // Per-step kernel of nets whose D history rows do not fit in 64 KB of LDS
 // (wide.hip).  `grid` workgroups per trial own gpw groups each and stage Dl

@@ -427,3 +427,29 @@ def test_batch_with_trials_and_mixed_paths(gpu, oracle):
     batch.close()
     for g in gs:
         g.close()
+
+
+def test_batch_compact_and_full_records(gpu, oracle):
+    """The batch kernel reads 4-byte record copies when every net allows them
+    (N <= 16384, delays <= 16, weights k * 2^-e with |k| <= 127) and the
+    8-byte records otherwise: a batch of compact nets, and the same batch
+    with one net whose weights need more (3.0 beside 1/64) and one with
+    delays up to 20."""
+    from paper_2305_02510_amd import Batch
+    base = [wl.random_small(3000 + i, n=[40, 300, 900][i % 3], p=0.08, max_delay=1 + i % 7, steps=70,
+                            trials=1 + i % 2, hetero=True) for i in range(6)]
+    wide_w = wl.random_small(3100, n=500, p=0.05, max_delay=5, steps=70)
+    wide_w.weight[::7] = 3.0
+    wide_w.weight[1::7] = 1 / 64
+    long_d = wl.large_sparse(3101, n=2000, p=0.01, steps=70, max_delay=20)
+    for nets in (base, base + [wide_w, long_d]):
+        gs = [gpu.from_workload(net) for net in nets]
+        batch = Batch(gs)
+        batch.run(25)
+        batch.run(45)
+        for net, g in zip(nets, gs):
+            res = oracle.run_sparse(net)
+            assert_parity(net, res, g.read_raster(0, net.steps), *g.read_state(), "batch")
+        batch.close()
+        for g in gs:
+            g.close()
