@@ -87,11 +87,11 @@ struct RecHeld<true> {
   using type = uint32_t;
 };
 
-template <bool RECS_LDS, bool COMPACT = false>
+template <bool RECS_LDS, bool COMPACT = false, int U = 4>
 __device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int start, int end, int lane, int r0,
-                                          typename RecHeld<COMPACT>::type (&rc)[4], bool (&valid)[4]) {
+                                          typename RecHeld<COMPACT>::type (&rc)[U], bool (&valid)[U]) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int k = start + lane + 64 * u;
     valid[u] = k < end;
     const int kc = k < end ? k : end - 1;
@@ -105,11 +105,11 @@ __device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int 
   }
 }
 
-template <bool COMPACT>
-__device__ __forceinline__ void expand_recs(const DevNet& n, const typename RecHeld<COMPACT>::type (&held)[4],
-                                            Rec (&rc)[4]) {
+template <bool COMPACT, int U = 4>
+__device__ __forceinline__ void expand_recs(const DevNet& n, const typename RecHeld<COMPACT>::type (&held)[U],
+                                            Rec (&rc)[U]) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     if constexpr (COMPACT) {
       rc[u] = expand_compact(held[u], n.cscale);
     } else {
@@ -130,15 +130,15 @@ __device__ __forceinline__ void expand_recs(const DevNet& n, const typename RecH
 //               row directly, a group split between ranges atomically.
 constexpr int kModeSlot = 0, kModeOwn = 1, kModeRange = 2;
 
-// The four records of one chunk held by a lane: source bits from the ring
+// The U records of one chunk held by a lane: source bits from the ring
 // (or the mailbox), own-post weights into *sum, other posts atomically.
-template <bool RECS_LDS, bool RING_LDS>
-__device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[4], const bool (&valid)[4],
+template <bool RECS_LDS, bool RING_LDS, int U = 4>
+__device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U], const bool (&valid)[U],
                                               const uint32_t* ring, const uint64_t* mring, float* acc_g, float& sum,
                                               int lane, int t, int cur, int Dr, int W32, uint32_t curW, uint32_t DrW) {
-  uint32_t bit[4];
+  uint32_t bit[U];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     const uint32_t mt = rc[u].meta;
     if (RING_LDS && RECS_LDS) {
       // staged records carry their ring offset (see lds_meta): the row of
@@ -167,43 +167,51 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[4
       }
     }
   }
+  bool other = false;  // an active overflow record of another lane's post (rare)
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) {
     const uint32_t post = rc[u].meta >> 26;
     sum += (bit[u] && post == static_cast<uint32_t>(lane)) ? rc[u].w : 0.f;
-    if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], rc[u].w);
+    other |= bit[u] && post != static_cast<uint32_t>(lane);
+  }
+  if (other) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t post = rc[u].meta >> 26;
+      if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], rc[u].w);
+    }
   }
 }
 
 // Slot mode: the chunks member, member + m, ... of the records [beg, end)
 // of one group part.  Returns the lane's own-post sum.
-template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false>
+template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false, int U = 4>
 __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec, const uint32_t* ring,
                                                const uint64_t* mring, float* acc_g, int beg, int end, int member,
                                                int m, int lane, int r0, int t, int cur, int Dr, int W32) {
   float sum = 0.f;
-  int start = beg + member * kChunk;
+  int start = beg + member * (64 * U);
   if (start >= end) return sum;
   const uint32_t curW = static_cast<uint32_t>(cur * W32);
   const uint32_t DrW = static_cast<uint32_t>(Dr * W32);
-  const int stride = m * kChunk;
+  const int stride = m * (64 * U);
   using Held = typename RecHeld<COMPACT>::type;
-  Held rc[4];
-  bool valid[4];
-  load_recs<RECS_LDS, COMPACT>(n, lrec, start, end, lane, r0, rc, valid);
+  Held rc[U];
+  bool valid[U];
+  load_recs<RECS_LDS, COMPACT, U>(n, lrec, start, end, lane, r0, rc, valid);
   for (; start < end; start += stride) {
-    Held nx[4];
-    bool nvalid[4];
-    if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS, COMPACT>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
-    Rec ex[4];
-    expand_recs<COMPACT>(n, rc, ex);
-    deliver_chunk<RECS_LDS, RING_LDS>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    Held nx[U];
+    bool nvalid[U];
+    if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS, COMPACT, U>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
+    Rec ex[U];
+    expand_recs<COMPACT, U>(n, rc, ex);
+    deliver_chunk<RECS_LDS, RING_LDS, U>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
     if (start + stride < end) {
       if (RECS_LDS) {
-        load_recs<RECS_LDS, COMPACT>(n, lrec, start + stride, end, lane, r0, rc, valid);
+        load_recs<RECS_LDS, COMPACT, U>(n, lrec, start + stride, end, lane, r0, rc, valid);
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
           rc[u] = nx[u];
           valid[u] = nvalid[u];
         }
@@ -223,7 +231,7 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
 // (Range: atomically unless the whole group lies in [lo, hi)).  Records of
 // other posts (overflow) are added into acc[lg][post] atomically.  Records
 // in global memory are prefetched one chunk ahead, across group changes.
-template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false>
+template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false, int U = 4>
 __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const uint32_t* ring,
                                          const uint64_t* mring, float* acc, const int* cs, const int* bp,
                                          const int* ep, int ng, int lg, int c, int cstride, int gstep, int lo, int hi,
@@ -243,9 +251,9 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
   // LDS only when the walk moves to another group)
   int beg = bp[lg], end = ep[lg], c0 = cs[lg], cend = item_end(lg);
   using Held = typename RecHeld<COMPACT>::type;
-  Held rc[4];
-  bool valid[4];
-  load_recs<RECS_LDS, COMPACT>(n, lrec, beg + (c - c0) * kChunk, end, lane, r0, rc, valid);
+  Held rc[U];
+  bool valid[U];
+  load_recs<RECS_LDS, COMPACT, U>(n, lrec, beg + (c - c0) * (64 * U), end, lane, r0, rc, valid);
   float sum = 0.f;
   for (;;) {
     // the next item
@@ -272,13 +280,13 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
       nc0 = cs[nlg];
       ncend = item_end(nlg);
     }
-    Held nx[4];
-    bool nvalid[4];
-    if (!RECS_LDS && more) load_recs<RECS_LDS, COMPACT>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, nx, nvalid);
+    Held nx[U];
+    bool nvalid[U];
+    if (!RECS_LDS && more) load_recs<RECS_LDS, COMPACT, U>(n, lrec, nbeg + (nc - nc0) * (64 * U), nend, lane, r0, nx, nvalid);
     float* acc_g = acc + lg * kGroup;
-    Rec ex[4];
-    expand_recs<COMPACT>(n, rc, ex);
-    deliver_chunk<RECS_LDS, RING_LDS>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    Rec ex[U];
+    expand_recs<COMPACT, U>(n, rc, ex);
+    deliver_chunk<RECS_LDS, RING_LDS, U>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
     if (!more || nlg != lg) {  // flush the group's register sum (uniform)
       if (mode == kModeSlot) {
         ret = sum;
@@ -291,10 +299,10 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
     }
     if (!more) break;
     if (RECS_LDS) {
-      load_recs<RECS_LDS, COMPACT>(n, lrec, nbeg + (nc - nc0) * kChunk, nend, lane, r0, rc, valid);
+      load_recs<RECS_LDS, COMPACT, U>(n, lrec, nbeg + (nc - nc0) * (64 * U), nend, lane, r0, rc, valid);
     } else {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         rc[u] = nx[u];
         valid[u] = nvalid[u];
       }
@@ -311,7 +319,7 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
 
 // PARAMS_LDS: neuron parameters live in LDS instead of registers (the batch
 // kernel, whose occupancy is bound by registers, not LDS).
-template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI, bool PARAMS_LDS = false, bool COMPACT = false>
+template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI, bool PARAMS_LDS = false, bool COMPACT = false, int U = 4>
 __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0, int steps, unsigned char* smem,
                                          int& abort_flag) {
   const DevNet& n = a.n;
@@ -363,8 +371,8 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
       const int s0 = n.gptr[g0 + i], s1 = n.gsplit[g0 + i], s2 = n.gptr[g0 + i + 1];
       csA[i] = ca;
       csB[i] = cb;
-      ca += (s1 - s0 + kChunk - 1) / kChunk;
-      cb += (s2 - s1 + kChunk - 1) / kChunk;
+      ca += (s1 - s0 + (64 * U) - 1) / (64 * U);
+      cb += (s2 - s1 + (64 * U) - 1) / (64 * U);
     }
     csA[ng] = ca;
     csB[ng] = cb;
@@ -471,10 +479,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     float sum = 0.f;
     if (mode == kModeSlot) {  // uniform per wave
       if (team < ng)
-        sum = deliver_group<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb + team * kGroup, gsp[team],
+        sum = deliver_group<RECS_LDS, RING_LDS, COMPACT, U>(n, lrec, ring, mring, accb + team * kGroup, gsp[team],
                                                 gsp[ng + 1 + team], member, m, lane, r0, t, cur, Dr, W32);
     } else if (wlg[0] < ng) {
-      deliver<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb, csA, gsp, gsp + ng + 1, ng, wlg[0], wc[0], cstride,
+      deliver<RECS_LDS, RING_LDS, COMPACT, U>(n, lrec, ring, mring, accb, csA, gsp, gsp + ng + 1, ng, wlg[0], wc[0], cstride,
                                   gstep, wlo[0], whi[0], mode, lane, r0, t, cur, Dr, W32);
     }
     if (receive) {
@@ -499,10 +507,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     // delay 1
     if (mode == kModeSlot) {
       if (team < ng)
-        sum += deliver_group<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb + team * kGroup, gsp[ng + 1 + team],
+        sum += deliver_group<RECS_LDS, RING_LDS, COMPACT, U>(n, lrec, ring, mring, accb + team * kGroup, gsp[ng + 1 + team],
                                                  gsp[team + 1], member, m, lane, r0, t, cur, Dr, W32);
     } else if (wlg[1] < ng) {
-      deliver<RECS_LDS, RING_LDS, COMPACT>(n, lrec, ring, mring, accb, csB, gsp + ng + 1, gsp + 1, ng, wlg[1], wc[1], cstride,
+      deliver<RECS_LDS, RING_LDS, COMPACT, U>(n, lrec, ring, mring, accb, csB, gsp + ng + 1, gsp + 1, ng, wlg[1], wc[1], cstride,
                                   gstep, wlo[1], whi[1], mode, lane, r0, t, cur, Dr, W32);
     }
     if (mode == kModeSlot) part[wave * kGroup + lane] = sum;  // partial sums for the updating wave
@@ -600,6 +608,12 @@ hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
 // queue is empty.  Team slices wait only on slices of the same network, all
 // of which are resident (cooperative launch) and start with their team task.
 // ---------------------------------------------------------------------------
+// Records per lane in one chunk of the batch kernel's record stream: 8 with
+// 4-byte records (twice the bytes in flight per wave, in the registers of 4
+// full records), else 4.
+template <bool COMPACT>
+constexpr int kBatchU = COMPACT ? 8 : 4;
+
 // COMPACT: every network of the batch has 4-byte record copies (n.crecs).
 template <bool COMPACT>
 __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, int steps) {
@@ -609,7 +623,8 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, 
   if (static_cast<int>(blockIdx.x) < ba.n_team) {
     const int4 tt = ba.team[blockIdx.x];
     const SimArgs a = ba.nets[tt.x].team;
-    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true, true, COMPACT>(a, tt.y, tt.z, tt.w, steps, smem,
+    if (!sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, true, true, COMPACT, kBatchU<COMPACT>>(
+            a, tt.y, tt.z, tt.w, steps, smem,
                                                                                    abort_flag))
       return;
   }
@@ -621,7 +636,8 @@ __global__ __launch_bounds__(kBatchThreads, 4) void k_batch(const BatchArgs ba, 
     if (i >= ba.n_queue) return;
     const int4 qt = ba.queue[i];
     const SimArgs a = ba.nets[qt.x].single;
-    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false, true, COMPACT>(a, 0, qt.y, qt.z, steps, smem,
+    sim_body<kBatchMaxGroups / (kBatchThreads / 64), false, true, false, true, COMPACT, kBatchU<COMPACT>>(
+        a, 0, qt.y, qt.z, steps, smem,
                                                                                abort_flag);
   }
 }
