@@ -54,6 +54,9 @@ struct sn_net {
   void* gsplit = nullptr;
   void* wsec = nullptr;  // delay-phase sections of the wide per-step kernel
   void* crecs = nullptr; // 4-byte record copies (compact_records), when the net allows them
+  void* lrecs = nullptr; // lane records of a lane-only layout (wide nets) and their offsets
+  void* lgptr = nullptr;
+  void* lwsec = nullptr;
   // persistent-kernel plans: one slice (SMALL) and several slices (PERSIST)
   struct DevPlan {
     SlicePlan host;
@@ -776,6 +779,21 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
   float cscale = 0.f;
   const std::vector<uint32_t> C = compact_records(L, n->d.N, n->d.D, &cscale);
+  // wide nets: a lane-only copy of the layout as 4-byte lane records, kept
+  // when it is at most 80% of the 8-byte records' bytes
+  std::vector<uint32_t> LR;
+  std::vector<int32_t> lgp, lws;
+  float lscale = 0.f;
+  if (wide_net(n->d) && n->d.N <= kLaneRecMaxNeurons && nnz > 0) {
+    HostLayout LL = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows, true);
+    if (!LL.too_large && LL.phases == L.phases && 4.0 * LL.recs.size() <= 0.8 * 8.0 * L.recs.size()) {
+      LR = lane_records(LL, n->d.N, &lscale);
+      if (!LR.empty()) {
+        lgp = std::move(LL.gptr);
+        lws = std::move(LL.wsec);
+      }
+    }
+  }
   SlicePlan one = partition_groups(L, n->d.G, 1, n->d.G);
   if (!fit_plan(n->d, one)) one.P = 0;
   SlicePlan many = plan_persist(n->d, L, n->slices_req);
@@ -788,20 +806,32 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   void* optr = dev_alloc(n, H.optr.size() * sizeof(int32_t));
   void* wsec = L.phases > 1 ? dev_alloc(n, L.wsec.size() * sizeof(int32_t)) : nullptr;
   void* crecs = C.empty() ? nullptr : dev_alloc(n, C.size() * sizeof(uint32_t));
-  bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec) || (!C.empty() && !crecs);
+  void* lrecs = LR.empty() ? nullptr : dev_alloc(n, LR.size() * sizeof(uint32_t));
+  void* lgptr = LR.empty() ? nullptr : dev_alloc(n, lgp.size() * sizeof(int32_t));
+  void* lwsec = LR.empty() || L.phases <= 1 ? nullptr : dev_alloc(n, lws.size() * sizeof(int32_t));
+  bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec) || (!C.empty() && !crecs) ||
+             (!LR.empty() && (!lrecs || !lgptr || (L.phases > 1 && !lwsec)));
   void* wg_one = alloc_plan(n, one, bad);
   void* wg_many = alloc_plan(n, many, bad);
   if (bad) {
-    for (void* p : {recs, gptr, gsplit, orecs, optr, wsec, crecs, wg_one, wg_many}) dev_free(n, p);
+    for (void* p : {recs, gptr, gsplit, orecs, optr, wsec, crecs, lrecs, lgptr, lwsec, wg_one, wg_many}) dev_free(n, p);
     return fail(SN_ENOMEM, "cannot allocate synapse records");
   }
   // the previous buffers may be in use by queued work
   SN_HIP(n, hipStreamSynchronize(n->stream));
   drop_graph(n);
-  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec, &n->crecs}) {
+  for (void** p : {&n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec, &n->crecs, &n->lrecs, &n->lgptr,
+                   &n->lwsec}) {
     dev_free(n, *p);
     *p = nullptr;
   }
+  n->lrecs = lrecs;
+  n->lgptr = lgptr;
+  n->lwsec = lwsec;
+  n->d.lrecs = static_cast<const uint32_t*>(lrecs);
+  n->d.lgptr = static_cast<const int32_t*>(lgptr);
+  n->d.lwsec = static_cast<const int32_t*>(lwsec);
+  n->d.lscale = lscale;
   n->recs = recs;
   n->gptr = gptr;
   n->gsplit = gsplit;
@@ -830,6 +860,12 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     SN_HIP(n, hipMemcpyAsync(wsec, L.wsec.data(), L.wsec.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   if (crecs)
     SN_HIP(n, hipMemcpyAsync(crecs, C.data(), C.size() * sizeof(uint32_t), hipMemcpyHostToDevice, n->stream));
+  if (lrecs) {
+    SN_HIP(n, hipMemcpyAsync(lrecs, LR.data(), LR.size() * sizeof(uint32_t), hipMemcpyHostToDevice, n->stream));
+    SN_HIP(n, hipMemcpyAsync(lgptr, lgp.data(), lgp.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+    if (lwsec)
+      SN_HIP(n, hipMemcpyAsync(lwsec, lws.data(), lws.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+  }
   SN_HIP(n, hipStreamSynchronize(n->stream));  // host vectors die at return
   st = install_plan(n, n->small, one, wg_one);
   if (st != SN_OK) return st;
@@ -938,11 +974,14 @@ sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const i
     void* r = dev_alloc(n, static_cast<size_t>(N) * pitch);
     if (!r) return fail(SN_ENOMEM, "cannot allocate %zu bytes of dense rows", static_cast<size_t>(N) * pitch);
     for (void** p : {&n->rows8, &n->wt, &n->wt8, &n->recs, &n->gptr, &n->gsplit, &n->orecs, &n->optr, &n->wsec,
-                     &n->crecs}) {
+                     &n->crecs, &n->lrecs, &n->lgptr, &n->lwsec}) {
       dev_free(n, *p);
       *p = nullptr;
     }
     n->d.crecs = nullptr;
+    n->d.lrecs = nullptr;
+    n->d.lgptr = nullptr;
+    n->d.lwsec = nullptr;
     n->d.recs = nullptr;
     n->d.gptr = nullptr;
     n->d.gsplit = nullptr;
@@ -1325,6 +1364,9 @@ void sn_destroy_network(sn_net* n) {
   dev_free(n, n->gsplit);
   dev_free(n, n->wsec);
   dev_free(n, n->crecs);
+  dev_free(n, n->lrecs);
+  dev_free(n, n->lgptr);
+  dev_free(n, n->lwsec);
   dev_free(n, n->small.wg);
   dev_free(n, n->persist.wg);
   dev_free(n, n->wt);

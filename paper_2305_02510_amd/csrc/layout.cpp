@@ -53,7 +53,7 @@ int64_t lane_rows(const std::vector<int64_t>& deg) {
 }  // namespace
 
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
-                        const uint8_t* delay, int32_t max_delay, int32_t phase_rows) {
+                        const uint8_t* delay, int32_t max_delay, int32_t phase_rows, bool lane_only) {
   HostLayout L;
   // delay phases (phase p: delays p * phase_rows + 1 .. (p + 1) * phase_rows);
   // part A holds the sections of phases P-1 .. 1, then phase 0 (delays >= 2)
@@ -108,7 +108,9 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
       }
       // a filler names neuron 0 with a delay of this section and weight -0
       const uint32_t fill_delay = part == 0 ? static_cast<uint32_t>(dlo) : 1u;
-      const int64_t R = lane_rows(deg);
+      int64_t R = lane_rows(deg);
+      if (lane_only)  // every synapse in its post's lane: as many rows as the largest in-degree
+        for (int l = 0; l < kGroup; ++l) R = std::max(R, deg[l]);
       for (int64_t r = 0; r < R; ++r) {
         for (int l = 0; l < kGroup; ++l) {
           if (deg[l] > r) {
@@ -158,6 +160,25 @@ std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t ma
     const Rec& r = L.recs[i];
     const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
     out[i] = compact_record(k, r.meta & 0xFFFFFu, ((r.meta >> 20) & 63u) + 1u, r.meta >> 26);
+  }
+  *scale = std::ldexp(1.f, -e);
+  return out;
+}
+
+std::vector<uint32_t> lane_records(const HostLayout& L, int32_t n, float* scale) {
+  std::vector<uint32_t> out;
+  if (n > kLaneRecMaxNeurons || L.recs.empty()) return out;
+  std::vector<float> w(L.recs.size());
+  for (size_t i = 0; i < w.size(); ++i) w[i] = L.recs[i].w;
+  const int32_t e = int8_exponent(w.data(), static_cast<int64_t>(w.size()));
+  if (e < 0) return out;
+  const float f = std::ldexp(1.f, e);
+  out.resize(L.recs.size());
+  for (size_t i = 0; i < out.size(); ++i) {
+    const Rec& r = L.recs[i];
+    if ((r.meta >> 26) != static_cast<uint32_t>(i % kGroup)) return {};  // not lane-owned
+    const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
+    out[i] = lane_record(k, r.meta & 0xFFFFFu, ((r.meta >> 20) & 63u) + 1u);
   }
   *scale = std::ldexp(1.f, -e);
   return out;

@@ -73,8 +73,21 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
 
 // phase_rows > 0 splits part A into delay phases of that many delays each
 // (see HostLayout), for nets of at least two phases; 0 = no phases.
+// lane_only: no overflow sections, every record in its post's lane (as many
+// rows as a part's largest in-degree).
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
-                        const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0);
+                        const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0, bool lane_only = false);
+
+// Lane record, 4 bytes, of a lane_only layout (the post is the lane), for
+// the wide per-step kernel, nets with N <= 2^18 and every weight k * 2^-e
+// with |k| <= 127:  bits 0..7 k (int8), bits 8..13 delay - 1, bits 14..31 pre.
+constexpr int32_t kLaneRecMaxNeurons = 1 << 18;
+__host__ __device__ inline uint32_t lane_record(int32_t k, uint32_t pre, uint32_t delay) {
+  return (static_cast<uint32_t>(k) & 0xFFu) | ((delay - 1u) << 8) | (pre << 14);
+}
+// 4-byte copies of a lane_only layout's records, or empty when a record is
+// not in its post's lane or a weight does not allow it; *scale = 2^-e.
+std::vector<uint32_t> lane_records(const HostLayout& L, int32_t n, float* scale);
 
 // Plain pointers and sizes handed to every kernel.
 struct DevNet {
@@ -107,6 +120,12 @@ struct DevNet {
   // 4-byte copies of the records (same order), or null: see compact_record
   const uint32_t* crecs;
   float cscale;           // 2^-e: weight = (int8 numerator) * cscale
+  // wide nets: lane records of a lane_only layout with the same delay phases
+  // (own offsets), or null: see lane_record
+  const uint32_t* lrecs;
+  const int32_t* lgptr;   // [G + 1]
+  const int32_t* lwsec;   // [G][phases]
+  float lscale;
 };
 
 // Compact record, 4 bytes, for nets with N <= 16384, delays <= 16 and every

@@ -27,6 +27,11 @@
 // members leave theirs in LDS slots that one member adds after the phase's
 // barrier.  After the last phase wave w updates groups g0 + w, g0 + w + 16,
 // ... and writes their spike words.
+//
+// LANE: the net also holds a lane-only copy of its layout (no overflow: every
+// record in its post's lane) as 4-byte lane records (int8 weight numerator,
+// delay, pre-neuron); the kernel then streams those, 16 per lane per batch,
+// half the bytes of the 8-byte records, with no atomic at all.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,8 +43,17 @@ namespace snmi {
 
 constexpr int kWideThreads = 1024;
 constexpr int kWideWaves = kWideThreads / 64;
-constexpr int kWideU = 8;                              // records per lane in one batch
-constexpr int kWideWaveBatch = 64 * kWideU;            // records of one wave's batch
+// records per lane in one batch: 8 records of 8 bytes, or 16 lane records
+template <bool LANE>
+constexpr int kWideU = LANE ? 16 : 8;
+template <bool LANE>
+struct WideRec {
+  using type = Rec;
+};
+template <>
+struct WideRec<true> {
+  using type = uint32_t;
+};
 constexpr int kWideNpw = 4;                            // groups updated per wave, at most
 constexpr int kWideStage = 8;                          // history words per thread in flight while staging
 constexpr size_t kWideStaticLds = kWideWaves * kGroup * sizeof(float) + 64;
@@ -49,24 +63,31 @@ constexpr size_t kStepRingLimitWide = 64 * 1024;  // below this the per-group ke
 // Loads are unconditional, from an index clamped into [0, end) (the records
 // array always holds at least one record's worth of memory), so all of them
 // stay in flight together; records past `end` are masked when delivered.
-__device__ __forceinline__ void wide_load(const Rec* __restrict__ recs, int base, int end, int lane,
-                                          Rec (&r)[kWideU]) {
+template <bool LANE>
+__device__ __forceinline__ void wide_load(const DevNet& n, int base, int end, int lane,
+                                          typename WideRec<LANE>::type (&r)[kWideU<LANE>]) {
 #pragma unroll
-  for (int u = 0; u < kWideU; ++u) r[u] = recs[max(0, min(base + u * 64 + lane, end - 1))];
+  for (int u = 0; u < kWideU<LANE>; ++u) {
+    const int k = max(0, min(base + u * 64 + lane, end - 1));
+    if constexpr (LANE) r[u] = n.lrecs[k];
+    else r[u] = n.recs[k];
+  }
 }
 
 // Records of group g in phase p: phase p >= 1 is the section [wsec[p],
 // wsec[p - 1]); phase 0 runs from wsec[0] to the group's end (delay-1 part
 // included).  Without phases: all records of the group.
+template <bool LANE>
 __device__ __forceinline__ void wide_range(const DevNet& n, int g, int p, int& beg, int& end) {
+  const int32_t* gp = LANE ? n.lgptr : n.gptr;
   if (n.phases <= 1) {
-    beg = n.gptr[g];
-    end = n.gptr[g + 1];
+    beg = gp[g];
+    end = gp[g + 1];
     return;
   }
-  const int32_t* ws = n.wsec + static_cast<size_t>(g) * n.phases;
+  const int32_t* ws = (LANE ? n.lwsec : n.wsec) + static_cast<size_t>(g) * n.phases;
   beg = ws[p];
-  end = p == 0 ? n.gptr[g + 1] : ws[p - 1];
+  end = p == 0 ? gp[g + 1] : ws[p - 1];
 }
 
 // A wave's walk over the records of one phase.  With ng >= 16 groups wave w
@@ -78,11 +99,14 @@ struct WidePair {
   bool valid;
 };
 
+template <bool LANE>
 __device__ __forceinline__ void wide_enter(const DevNet& n, WidePair& s, int p) {
-  wide_range(n, s.g, p, s.beg, s.end);
-  s.nb = max(1, (s.end - s.beg + kWideWaveBatch - 1) / kWideWaveBatch);
+  constexpr int batch = 64 * kWideU<LANE>;
+  wide_range<LANE>(n, s.g, p, s.beg, s.end);
+  s.nb = max(1, (s.end - s.beg + batch - 1) / batch);
 }
 
+template <bool LANE>
 __device__ __forceinline__ WidePair wide_start(const DevNet& n, int p, int g0, int g1, bool own, int team,
                                                int member) {
   WidePair s{};
@@ -90,12 +114,13 @@ __device__ __forceinline__ WidePair wide_start(const DevNet& n, int p, int g0, i
   s.k = own ? 0 : member;
   s.valid = s.g < g1;
   if (s.valid) {
-    wide_enter(n, s, p);
+    wide_enter<LANE>(n, s, p);
     s.valid = s.k < s.nb;
   }
   return s;
 }
 
+template <bool LANE>
 __device__ __forceinline__ WidePair wide_next(const DevNet& n, const WidePair& s, int p, int g1, int m, bool own) {
   WidePair r = s;
   if (!s.valid) return r;
@@ -106,26 +131,31 @@ __device__ __forceinline__ WidePair wide_next(const DevNet& n, const WidePair& s
       r.g = s.g + kWideWaves;
       r.k = 0;
       r.valid = r.g < g1;
-      if (r.valid) wide_enter(n, r, p);
+      if (r.valid) wide_enter<LANE>(n, r, p);
     }
   }
   return r;
 }
 
-__device__ __forceinline__ int wide_first(const WidePair& s) { return s.beg + s.k * kWideWaveBatch; }
+template <bool LANE>
+__device__ __forceinline__ int wide_first(const WidePair& s) { return s.beg + s.k * (64 * kWideU<LANE>); }
 
 // A pair past the wave's last one loads (and never delivers) that last
 // pair's records again.
-__device__ __forceinline__ void wide_load_pair(const Rec* __restrict__ recs, const WidePair& s, int lane,
-                                               Rec (&r)[kWideU]) {
-  wide_load(recs, wide_first(s), s.end, lane, r);
+template <bool LANE>
+__device__ __forceinline__ void wide_load_pair(const DevNet& n, const WidePair& s, int lane,
+                                               typename WideRec<LANE>::type (&r)[kWideU<LANE>]) {
+  wide_load<LANE>(n, wide_first<LANE>(s), s.end, lane, r);
 }
 
 // FALLBACK: no delay phases and more delays than staged rows; delays above
 // the staged rows read the raster in memory.
 // NPW: groups one wave updates at most (1 when a workgroup has <= 16).
-template <bool FALLBACK, int NPW>
+// LANE: lane records (n.lrecs, n.lgptr, n.lwsec).
+template <bool FALLBACK, int NPW, bool LANE>
 __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int t, int Dl, int P) {
+  constexpr int U = kWideU<LANE>;
+  using Held = typename WideRec<LANE>::type;
   extern __shared__ __align__(16) uint32_t smem[];
   __shared__ float part[kWideWaves][kGroup];
   const int b = blockIdx.y;
@@ -202,25 +232,31 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
     // this wave's (group, batch) walk: no barrier until the phase ends, three
     // record buffers in rotation keep two batches in flight while one is
     // delivered (no buffer is copied: a copy would wait for its load)
-    WidePair s0 = wide_start(n, p, g0, g1, own, team, member);
-    WidePair s1 = wide_next(n, s0, p, g1, m, own), s2 = wide_next(n, s1, p, g1, m, own);
-    Rec b0[kWideU], b1[kWideU], b2[kWideU];
-    wide_load_pair(n.recs, s0, lane, b0);
-    wide_load_pair(n.recs, s1, lane, b1);
-    wide_load_pair(n.recs, s2, lane, b2);
+    WidePair s0 = wide_start<LANE>(n, p, g0, g1, own, team, member);
+    WidePair s1 = wide_next<LANE>(n, s0, p, g1, m, own), s2 = wide_next<LANE>(n, s1, p, g1, m, own);
+    Held b0[U], b1[U], b2[U];
+    wide_load_pair<LANE>(n, s0, lane, b0);
+    wide_load_pair<LANE>(n, s1, lane, b1);
+    wide_load_pair<LANE>(n, s2, lane, b2);
     float sum = 0.f;
     // delivers the batch of pair sc; an owned group's sum is added to its row
     // when the walk leaves it; false when sc was the wave's last pair
-    auto body = [&](const WidePair& sc, const Rec (&cur)[kWideU], const WidePair& sn) -> bool {
+    auto body = [&](const WidePair& sc, const Held (&cur)[U], const WidePair& sn) -> bool {
       if (!sc.valid) return false;
       float* acc_g = gacc + (sc.g - g0) * kGroup;
-      const int first = wide_first(sc) + lane;
-      uint32_t bit[kWideU];
+      const int first = wide_first<LANE>(sc) + lane;
+      uint32_t bit[U];
 #pragma unroll
-      for (int u = 0; u < kWideU; ++u) {
-        const uint32_t mt = cur[u].meta;
-        const int d = static_cast<int>((mt >> 20) & 63u) + 1;
-        const uint32_t pre = mt & 0xFFFFFu;
+      for (int u = 0; u < U; ++u) {
+        int d;
+        uint32_t pre;
+        if constexpr (LANE) {
+          d = static_cast<int>((cur[u] >> 8) & 63u) + 1;
+          pre = cur[u] >> 14;
+        } else {
+          d = static_cast<int>((cur[u].meta >> 20) & 63u) + 1;
+          pre = cur[u].meta & 0xFFFFFu;
+        }
         const bool valid = first + u * 64 < sc.end;
         const int r = d - dbase - 1;  // row of the phase's staged rows
         if (!FALLBACK) {
@@ -237,18 +273,24 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
                        : 0u;
         }
       }
-      bool other = false;  // an active overflow record of another lane's post
+      if constexpr (LANE) {  // every record is of this lane's post
 #pragma unroll
-      for (int u = 0; u < kWideU; ++u) {
-        const uint32_t post = cur[u].meta >> 26;
-        sum += (bit[u] && post == static_cast<uint32_t>(lane)) ? cur[u].w : 0.f;
-        other |= bit[u] && post != static_cast<uint32_t>(lane);
-      }
-      if (other) {  // rare: overflow records follow the lane-owned rows
+        for (int u = 0; u < U; ++u)
+          sum += bit[u] ? static_cast<float>(static_cast<int8_t>(cur[u] & 0xFFu)) * n.lscale : 0.f;
+      } else {
+        bool other = false;  // an active overflow record of another lane's post
 #pragma unroll
-        for (int u = 0; u < kWideU; ++u) {
+        for (int u = 0; u < U; ++u) {
           const uint32_t post = cur[u].meta >> 26;
-          if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], cur[u].w);
+          sum += (bit[u] && post == static_cast<uint32_t>(lane)) ? cur[u].w : 0.f;
+          other |= bit[u] && post != static_cast<uint32_t>(lane);
+        }
+        if (other) {  // rare: overflow records follow the lane-owned rows
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const uint32_t post = cur[u].meta >> 26;
+            if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], cur[u].w);
+          }
         }
       }
       if (own && (!sn.valid || sn.g != sc.g)) {  // an owned group: this wave is its only contributor
@@ -259,14 +301,14 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
     };
     for (;;) {
       if (!body(s0, b0, s1)) break;
-      const WidePair s3 = wide_next(n, s2, p, g1, m, own);
-      wide_load_pair(n.recs, s3, lane, b0);
+      const WidePair s3 = wide_next<LANE>(n, s2, p, g1, m, own);
+      wide_load_pair<LANE>(n, s3, lane, b0);
       if (!body(s1, b1, s2)) break;
-      const WidePair s4 = wide_next(n, s3, p, g1, m, own);
-      wide_load_pair(n.recs, s4, lane, b1);
+      const WidePair s4 = wide_next<LANE>(n, s3, p, g1, m, own);
+      wide_load_pair<LANE>(n, s4, lane, b1);
       if (!body(s2, b2, s3)) break;
-      const WidePair s5 = wide_next(n, s4, p, g1, m, own);
-      wide_load_pair(n.recs, s5, lane, b2);
+      const WidePair s5 = wide_next<LANE>(n, s4, p, g1, m, own);
+      wide_load_pair<LANE>(n, s5, lane, b2);
       s0 = s3;
       s1 = s4;
       s2 = s5;
@@ -333,10 +375,14 @@ hipError_t prepare_wide_kernel(const DevNet& n, int cus) {
   const int Dl = wide_rows_of(n, w);
   if (Dl < 1 || wide_lds(n, w, Dl) + kWideStaticLds > kWideLdsLimit) return hipErrorInvalidValue;
   const int bytes = static_cast<int>(wide_lds(n, w, Dl));
-  const void* fns[] = {reinterpret_cast<const void*>(&k_step_wide<false, 1>),
-                       reinterpret_cast<const void*>(&k_step_wide<true, 1>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw>),
-                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_step_wide<false, 1, false>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, 1, false>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, false>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw, false>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, 1, true>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw, true>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -353,13 +399,20 @@ hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) 
   const bool fallback = P == 1 && Dl < n.D;
   const dim3 grid(w.grid, n.B), block(kWideThreads);
   const size_t lds = wide_lds(n, w, Dl);
-  if (w.gpw <= kWideWaves) {
-    if (fallback) hipLaunchKernelGGL((k_step_wide<true, 1>), grid, block, lds, s, n, t, Dl, P);
-    else hipLaunchKernelGGL((k_step_wide<false, 1>), grid, block, lds, s, n, t, Dl, P);
-  } else {
-    if (fallback) hipLaunchKernelGGL((k_step_wide<true, kWideNpw>), grid, block, lds, s, n, t, Dl, P);
-    else hipLaunchKernelGGL((k_step_wide<false, kWideNpw>), grid, block, lds, s, n, t, Dl, P);
+  const bool lane = n.lrecs != nullptr;
+#define SN_WIDE(FB, NPW, LN) hipLaunchKernelGGL((k_step_wide<FB, NPW, LN>), grid, block, lds, s, n, t, Dl, P)
+  const int key = (fallback ? 1 : 0) + (w.gpw <= kWideWaves ? 0 : 2) + (lane ? 4 : 0);
+  switch (key) {
+    case 0: SN_WIDE(false, 1, false); break;
+    case 1: SN_WIDE(true, 1, false); break;
+    case 2: SN_WIDE(false, kWideNpw, false); break;
+    case 3: SN_WIDE(true, kWideNpw, false); break;
+    case 4: SN_WIDE(false, 1, true); break;
+    case 5: SN_WIDE(true, 1, true); break;
+    case 6: SN_WIDE(false, kWideNpw, true); break;
+    default: SN_WIDE(true, kWideNpw, true); break;
   }
+#undef SN_WIDE
   return hipGetLastError();
 }
 
