@@ -399,6 +399,7 @@ def bench_batch(args, steps=None, warmup=None):
     batch.synchronize()
     setup_s = time.perf_counter() - t_setup
     stream = gs[0].stream
+    tuned = batch.autotune(min(T, 100)) if args.path == "autotune" else None  # the schedule autotuner
 
     def batched():
         for g in gs:
@@ -427,7 +428,8 @@ def bench_batch(args, steps=None, warmup=None):
            "neuron_updates_per_s": neurons * T / (ms_b / 1e3), "setup_s": setup_s,
            "plain_ms_per_run": round(ms_p, 4) if ms_p else None,
            "batched_speedup_vs_plain": round(ms_p / ms_b, 3) if ms_p else None,
-           "nets": len(nets), "total_neurons": neurons, "total_synapses": nnz}
+           "nets": len(nets), "total_neurons": neurons, "total_synapses": nnz,
+           "schedule": {"target_mult": tuned[0], "team_share": tuned[1]} if tuned else None}
     traffic = measured_traffic("uneven_batch_k_batch_hbm_traffic.txt", "kernels.hip")
     out["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -663,6 +665,8 @@ def main():
     for k in ("plain_ms_per_run", "batched_speedup_vs_plain", "ms_per_step_median"):
         if k in r:
             out[k] = r[k]
+    if r.get("schedule"):
+        out["config"]["schedule_autotuned"] = r["schedule"]
     if "ms_per_step_median" not in out:
         out["ms_per_step_median"] = round(LAST_TIMING.get("median_ms", float("nan")), 4)
     if args.workload == "large_sparse" and not args.no_batch:
@@ -682,7 +686,8 @@ def main():
             "neuron_updates_per_s": round(rb["neuron_updates_per_s"], 1),
             "events_per_run": rb["events_per_run"], "roofline": rb["roofline"],
             "cpu_baseline": rb.get("cpu_baseline"), "parity_bit_exact": rb.get("parity_bit_exact"),
-            "parity_sample": rb.get("parity_sample"), "setup_s": round(rb["setup_s"], 3)}
+            "parity_sample": rb.get("parity_sample"), "setup_s": round(rb["setup_s"], 3),
+            "schedule_autotuned": rb.get("schedule")}
     print(json.dumps(out), flush=True)
 
 

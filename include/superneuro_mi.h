@@ -296,6 +296,21 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out);
  * (poisons the batch and its networks). */
 sn_status sn_batch_run(sn_batch* batch, int32_t n_steps);
 
+/* Schedule autotuner of a batch (the batching direction: a schedule per
+ * size class of networks): times candidate schedules of the batch -- how
+ * large a share of one step's records a slice of a network may take before
+ * the network is split across a team of workgroups (as a multiple of the
+ * average load per workgroup), and what share of the workgroups teams may
+ * occupy, the rest running the smaller networks from the queue -- over
+ * `steps` steps from the initial state, each after one untimed run of the
+ * same length, with HIP events on the batch's stream, and keeps the fastest.
+ * Results do not depend on the schedule.  Every network of the batch is
+ * reset (t = 0) before every candidate and at the end; external spikes are
+ * kept.  *target_mult_out / *team_share_out (either may be NULL) receive the
+ * chosen knobs (sn_batch_create uses 1.0 and 0.75).  1 <= steps <= 4096, else
+ * SN_ERANGE; SN_ESTATE as sn_batch_run; a device error poisons the batch. */
+sn_status sn_batch_autotune(sn_batch* batch, int32_t steps, float* target_mult_out, float* team_share_out);
+
 /* Frees the batch (not its networks).  NULL is ignored. */
 void sn_batch_destroy(sn_batch* batch);
 

@@ -22,7 +22,7 @@ EXPORTS = [
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_autotune", "sn_get_progress", "sn_destroy_network",
     "sn_last_error", "sn_set_stdp", "sn_read_weights",
-    "sn_batch_create", "sn_batch_run", "sn_batch_destroy",
+    "sn_batch_create", "sn_batch_run", "sn_batch_destroy", "sn_batch_autotune",
     "sn_bptt_workspace_bytes", "sn_bptt_forward", "sn_bptt_backward", "sn_bptt_forward_noalloc",
 ]
 
@@ -89,6 +89,7 @@ def load():
         "sn_get_progress": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "sn_batch_create": [P, I32, ctypes.POINTER(P)],
         "sn_batch_run": [P, I32],
+        "sn_batch_autotune": [P, I32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -395,6 +395,11 @@ struct sn_batch {
   void* head_buf = nullptr;
   int grid = 0;
   size_t lds = 0;
+  // schedule knobs (sn_batch_autotune): the per-slice cost target as a
+  // multiple of the average load per workgroup, and the share of the
+  // workgroups that teams of slices may take (the rest run the queue)
+  float target_mult = 1.f;
+  float team_share = 0.75f;
   bool poisoned = false;
 };
 
@@ -409,6 +414,93 @@ void batch_free(sn_batch* bt) {
   dev_free(a, bt->queue_buf);
   dev_free(a, bt->head_buf);
   bt->plan_buf = bt->nets_buf = bt->team_buf = bt->queue_buf = bt->head_buf = nullptr;
+}
+
+// Plans the batch's schedule with the given knobs: how many slices every
+// network gets (a team when more than one), the team tasks (largest first,
+// slices of a team contiguous) and the queue, and their device tables.  The
+// old tables are freed only once the new ones are in place.
+sn_status plan_batch(sn_batch* bt, float target_mult, float team_share) {
+  const std::vector<sn_net*>& v = bt->nets;
+  const int32_t count = static_cast<int32_t>(v.size());
+  // cost of one step of one trial: records streamed plus neuron updates
+  std::vector<double> cost(count);
+  double total = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    cost[k] = static_cast<double>(v[k]->d.nnz) + 4.0 * v[k]->d.Npad;
+    total += cost[k] * v[k]->d.B;
+  }
+  // team sizes: no slice above ~target; teams take at most team_share of the workgroups
+  double target = std::max(1.0, total / bt->grid * target_mult);
+  const int64_t team_cap = static_cast<int64_t>(team_share * bt->grid);
+  std::vector<int32_t> P(count);
+  for (int iter = 0; iter < 200; ++iter) {
+    int64_t team_wgs = 0;
+    for (int32_t k = 0; k < count; ++k) {
+      const int32_t G = v[k]->d.G;
+      int32_t p = std::max<int32_t>((G + kBatchMaxGroups - 1) / kBatchMaxGroups,
+                                    static_cast<int32_t>(std::min(1e9, std::ceil(cost[k] / target))));
+      p = std::min(p, G);
+      p = std::min(p, std::max(1, kMaxCoopGroups / v[k]->d.B));  // slice flags hold 256 slices per trial
+      P[k] = p;
+      if (p > 1) team_wgs += static_cast<int64_t>(p) * v[k]->d.B;
+    }
+    if (team_wgs <= team_cap) break;
+    target *= 1.25;
+  }
+  std::vector<SlicePlan> plans(count);
+  std::vector<size_t> plan_off(count);
+  std::vector<int32_t> tables;
+  for (int32_t k = 0; k < count; ++k) {
+    SlicePlan p = partition_groups(v[k]->layout, v[k]->d.G, P[k], kBatchMaxGroups);
+    if (p.ng_max > kBatchMaxGroups) return fail(SN_ERANGE, "network %d: too many neurons for a batch", k);
+    plan_off[k] = tables.size();
+    tables.insert(tables.end(), p.wg_group.begin(), p.wg_group.end());
+    plans[k] = std::move(p);
+  }
+  std::vector<int32_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  std::vector<int4> team, queue;
+  for (int32_t k : order) {
+    if (plans[k].P > 1) {
+      for (int32_t b = 0; b < v[k]->d.B; ++b)
+        for (int32_t w = 0; w < plans[k].P; ++w) team.push_back(make_int4(k, w, b, 0));
+    } else {
+      for (int32_t b = 0; b < v[k]->d.B; ++b) queue.push_back(make_int4(k, b, 0, 0));
+    }
+  }
+  if (static_cast<int64_t>(team.size()) > bt->grid) return fail(SN_ERANGE, "batch teams need more workgroups than the device holds");
+  sn_net* a = v[0];
+  void* plan_buf = dev_alloc(a, tables.size() * sizeof(int32_t));
+  void* nets_buf = dev_alloc(a, count * sizeof(BatchNet));
+  void* team_buf = dev_alloc(a, std::max<size_t>(1, team.size()) * sizeof(int4));
+  void* queue_buf = dev_alloc(a, std::max<size_t>(1, queue.size()) * sizeof(int4));
+  void* head_buf = dev_alloc(a, 256);
+  if (!plan_buf || !nets_buf || !team_buf || !queue_buf || !head_buf) {
+    for (void* p : {plan_buf, nets_buf, team_buf, queue_buf, head_buf}) dev_free(a, p);
+    return fail(SN_ENOMEM, "cannot allocate batch tables");
+  }
+  if (hipStreamSynchronize(bt->stream) != hipSuccess ||  // queued batch launches may read the old tables
+      hipMemcpyAsync(plan_buf, tables.data(), tables.size() * sizeof(int32_t), hipMemcpyHostToDevice, bt->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(bt->stream) != hipSuccess) {
+    for (void* p : {plan_buf, nets_buf, team_buf, queue_buf, head_buf}) dev_free(a, p);
+    return fail(SN_EDEVICE, "cannot upload batch tables");
+  }
+  batch_free(bt);
+  bt->plan_buf = plan_buf;
+  bt->nets_buf = nets_buf;
+  bt->team_buf = team_buf;
+  bt->queue_buf = queue_buf;
+  bt->head_buf = head_buf;
+  bt->plans = std::move(plans);
+  bt->plan_off = std::move(plan_off);
+  bt->team = std::move(team);
+  bt->queue = std::move(queue);
+  bt->target_mult = target_mult;
+  bt->team_share = team_share;
+  return SN_OK;
 }
 
 }  // namespace
@@ -441,13 +533,6 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     (void)hipGetLastError();
     return fail(SN_EDEVICE, "cannot query the device");
   }
-  // cost of one step of one trial: records streamed plus neuron updates
-  std::vector<double> cost(count);
-  double total = 0;
-  for (int32_t k = 0; k < count; ++k) {
-    cost[k] = static_cast<double>(v[k]->d.nnz) + 4.0 * v[k]->d.Npad;
-    total += cost[k] * v[k]->d.B;
-  }
   sn_batch* bt = new (std::nothrow) sn_batch();
   if (!bt) return fail(SN_ENOMEM, "out of host memory");
   bt->nets = v;
@@ -464,72 +549,12 @@ sn_status sn_batch_create(sn_net* const* nets, int32_t count, sn_batch** out) {
     return fail(SN_ERANGE, "batch kernel does not fit on a compute unit");
   }
   bt->grid = per_cu * cus;
-  // team sizes: no slice above ~the average load; teams use at most 3/4 of the workgroups
-  double target = total / bt->grid;
-  std::vector<int32_t> P(count);
-  for (int iter = 0; iter < 64; ++iter) {
-    int64_t team_wgs = 0;
-    for (int32_t k = 0; k < count; ++k) {
-      const int32_t G = v[k]->d.G;
-      int32_t p = std::max<int32_t>((G + kBatchMaxGroups - 1) / kBatchMaxGroups,
-                                    static_cast<int32_t>(std::ceil(cost[k] / target)));
-      p = std::min(p, G);
-      p = std::min(p, std::max(1, kMaxCoopGroups / v[k]->d.B));  // slice flags hold 256 slices per trial
-      P[k] = p;
-      if (p > 1) team_wgs += static_cast<int64_t>(p) * v[k]->d.B;
-    }
-    if (team_wgs <= (3 * static_cast<int64_t>(bt->grid)) / 4) break;
-    target *= 1.25;
-  }
-  // slice plans and their device tables
-  bt->plans.resize(count);
-  bt->plan_off.resize(count);
-  std::vector<int32_t> tables;
-  for (int32_t k = 0; k < count; ++k) {
-    sn_net* n = v[k];
-    SlicePlan p = partition_groups(n->layout, n->d.G, P[k], kBatchMaxGroups);
-    if (p.ng_max > kBatchMaxGroups) {
-      delete bt;
-      return fail(SN_ERANGE, "network %d: too many neurons for a batch", k);
-    }
-    bt->plan_off[k] = tables.size();
-    tables.insert(tables.end(), p.wg_group.begin(), p.wg_group.end());
-    bt->plans[k] = std::move(p);
-  }
   bt->lds = lds;
-  // tasks: teams first (largest first, slices of a team contiguous), then the queue
-  std::vector<int32_t> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
-  for (int32_t k : order) {
-    if (bt->plans[k].P > 1) {
-      for (int32_t b = 0; b < v[k]->d.B; ++b)
-        for (int32_t w = 0; w < bt->plans[k].P; ++w) bt->team.push_back(make_int4(k, w, b, 0));
-    } else {
-      for (int32_t b = 0; b < v[k]->d.B; ++b) bt->queue.push_back(make_int4(k, b, 0, 0));
-    }
-  }
-  if (static_cast<int64_t>(bt->team.size()) > bt->grid) {
-    delete bt;
-    return fail(SN_ERANGE, "batch teams need more workgroups than the device holds");
-  }
-  sn_net* a = v[0];
-  bt->plan_buf = dev_alloc(a, tables.size() * sizeof(int32_t));
-  bt->nets_buf = dev_alloc(a, count * sizeof(BatchNet));
-  bt->team_buf = dev_alloc(a, std::max<size_t>(1, bt->team.size()) * sizeof(int4));
-  bt->queue_buf = dev_alloc(a, std::max<size_t>(1, bt->queue.size()) * sizeof(int4));
-  bt->head_buf = dev_alloc(a, 256);
-  if (!bt->plan_buf || !bt->nets_buf || !bt->team_buf || !bt->queue_buf || !bt->head_buf) {
+  const sn_status st = plan_batch(bt, 1.f, 0.75f);
+  if (st != SN_OK) {
     batch_free(bt);
     delete bt;
-    return fail(SN_ENOMEM, "cannot allocate batch tables");
-  }
-  if (hipMemcpyAsync(bt->plan_buf, tables.data(), tables.size() * sizeof(int32_t), hipMemcpyHostToDevice, bt->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(bt->stream) != hipSuccess) {
-    batch_free(bt);
-    delete bt;
-    return fail(SN_EDEVICE, "cannot upload batch tables");
+    return st;
   }
   *out = bt;
   return SN_OK;
@@ -645,6 +670,78 @@ sn_status sn_bptt_backward(const sn_bptt_desc* d, const float* W_cat, const floa
   if (!W_cat || !x || !dcounts || !workspace || !dW_cat) return fail(SN_EINVAL, "null pointer");
   const hipError_t e = bptt_backward(*d, W_cat, x, dcounts, workspace, dW_cat, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(SN_EDEVICE, "BPTT backward: %s", hipGetErrorString(e));
+  return SN_OK;
+}
+
+sn_status sn_batch_autotune(sn_batch* bt, int32_t steps, float* target_mult_out, float* team_share_out) {
+  if (!bt) return fail(SN_EINVAL, "batch is NULL");
+  if (bt->poisoned) return fail(SN_ESTATE, "batch is poisoned by an earlier device error");
+  if (steps < 1 || steps > 4096) return fail(SN_ERANGE, "steps %d outside [1, 4096]", steps);
+  for (sn_net* n : bt->nets) {
+    const sn_status st = check_usable(n);
+    if (st != SN_OK) return st;
+  }
+  struct Cand {
+    float target_mult, team_share;
+  };
+  const Cand cands[] = {{1.f, 0.75f}, {0.5f, 0.75f}, {2.f, 0.75f}, {1.f, 0.5f}, {0.5f, 0.5f},
+                        {1.f, 0.875f}, {0.5f, 0.875f}, {0.25f, 0.875f}};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(SN_EDEVICE, "cannot create events");
+  }
+  auto reset_all = [&]() -> sn_status {
+    for (sn_net* n : bt->nets) {
+      const sn_status st = sn_reset_state(n);
+      if (st != SN_OK) return st;
+      if (n->stream != bt->stream && hipStreamSynchronize(n->stream) != hipSuccess) return fail(SN_EDEVICE, "sync");
+    }
+    return SN_OK;
+  };
+  Cand best{0.f, 0.f};
+  float best_ms = 0.f;
+  sn_status st = SN_OK;
+  for (const Cand& c : cands) {
+    st = plan_batch(bt, c.target_mult, c.team_share);
+    if (st == SN_ERANGE) {  // this schedule cannot run the batch
+      st = SN_OK;
+      continue;
+    }
+    if (st != SN_OK) break;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && st == SN_OK; ++rep) {  // untimed run, then the timed one
+      st = reset_all();
+      if (st == SN_OK && hipEventRecord(e0, bt->stream) != hipSuccess) st = fail(SN_EDEVICE, "hipEventRecord");
+      if (st == SN_OK) st = sn_batch_run(bt, steps);
+      if (st == SN_OK && hipEventRecord(e1, bt->stream) != hipSuccess) st = fail(SN_EDEVICE, "hipEventRecord");
+      if (st == SN_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(SN_EDEVICE, "hipEventSynchronize");
+      if (st == SN_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = fail(SN_EDEVICE, "hipEventElapsedTime");
+    }
+    if (st != SN_OK) break;
+    for (sn_net* n : bt->nets) {
+      st = check_status(n);  // a spike-exchange wait that timed out poisons the network
+      if (st != SN_OK) break;
+    }
+    if (st != SN_OK) break;
+    if (best.target_mult == 0.f || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SN_OK) {
+    bt->poisoned = bt->poisoned || std::any_of(bt->nets.begin(), bt->nets.end(), [](sn_net* n) { return n->poisoned; });
+    return st;
+  }
+  if (best.target_mult == 0.f) return fail(SN_ERANGE, "no schedule could run the batch");
+  st = plan_batch(bt, best.target_mult, best.team_share);
+  if (st == SN_OK) st = reset_all();
+  if (st != SN_OK) return st;
+  if (target_mult_out) *target_mult_out = best.target_mult;
+  if (team_share_out) *team_share_out = best.team_share;
   return SN_OK;
 }
 

@@ -261,6 +261,13 @@ class Batch:
     def run(self, steps: int):
         check(self.lib.sn_batch_run(self.h, int(steps)))
 
+    def autotune(self, steps: int = 64):
+        """sn_batch_autotune: picks the fastest schedule over `steps` steps
+        (every network is reset); returns (target_mult, team_share)."""
+        tm, ts = ctypes.c_float(), ctypes.c_float()
+        check(self.lib.sn_batch_autotune(self.h, int(steps), ctypes.byref(tm), ctypes.byref(ts)))
+        return float(tm.value), float(ts.value)
+
     def synchronize(self):
         if self.networks:
             self.networks[0].synchronize()

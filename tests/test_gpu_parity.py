@@ -453,3 +453,25 @@ def test_batch_compact_and_full_records(gpu, oracle):
         batch.close()
         for g in gs:
             g.close()
+
+
+def test_batch_schedule_autotune(gpu, oracle):
+    """The batch schedule autotuner leaves the networks reset and a schedule
+    that runs them bit-exact; every candidate schedule gives the same result."""
+    from paper_2305_02510_amd import Batch
+    nets = wl.uneven_batch(9, count=24, steps=80, n_range=(50, 2500), p_range=(0.01, 0.15))
+    gs = [gpu.from_workload(net) for net in nets]
+    for g in gs[:3]:
+        g.run(5)
+    batch = Batch(gs)
+    tm, ts = batch.autotune(40)
+    assert tm > 0 and 0 < ts <= 1
+    assert all(g.progress[0] == 0 for g in gs)
+    batch.run(30)
+    batch.run(50)
+    for net, g in zip(nets, gs):
+        res = oracle.run_sparse(net)
+        assert_parity(net, res, g.read_raster(0, net.steps), *g.read_state(), f"batch after autotune {tm}/{ts}")
+    batch.close()
+    for g in gs:
+        g.close()
