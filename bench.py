@@ -194,14 +194,20 @@ def bench_single(args, net, kind):
     else:
         bytes_step = algorithmic_bytes_per_step(ev, T, net.n, net.trials)
         achieved = bytes_step / sec_per_tstep / 1e9
-        kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)", "step": "k_step",
-                  "push": "k_push"}.get(path, path)
+        # the per-step path stages the spike history through LDS in delay
+        # phases (k_step_wide) once its 2*D words per 64-neuron group pass 64 KiB
+        wide = 8 * net.max_delay * -(-net.n // 64) > 64 * 1024
+        kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)",
+                  "step": "k_step_wide" if wide else "k_step", "push": "k_push"}.get(path, path)
         if kind == "stdp":
             kernel = "k_step + k_stdp (per step)"
         traffic = None
         if path == "persist" and net.name.startswith("large_sparse_n10000") and (tuned is None or tuned[1] == 0):
             # counters taken on the default slice plan
             traffic = measured_traffic("large_sparse_k_sim_persist_hbm_traffic.txt", "kernels.hip")
+        for p_xl in ("0.01", "0.001"):
+            if path == "step" and wide and net.name == f"large_sparse_xl_n100000_p{p_xl}":
+                traffic = measured_traffic(f"large_sparse_xl_p{p_xl}_k_step_wide_hbm_traffic.txt", "wide.hip")
         out["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),

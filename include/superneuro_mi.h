@@ -199,6 +199,22 @@ sn_status sn_read_raster(sn_net* net, int32_t t0, int32_t n_steps, uint32_t* out
  * the work in flight. */
 sn_status sn_read_state(sn_net* net, float* V, uint8_t* refractory_left);
 
+/* Device-memory variants of sn_read_raster and sn_read_state, for callers
+ * that keep the results on the GPU (as input of their own kernels, or to
+ * overlap the readback with host work).  Same layouts; `out`, `V` and
+ * `refractory_left` are device memory of the network's device, owned by the
+ * caller and not overlapping the network's own buffers.  Asynchronous on the
+ * network's stream: they enqueue a repack kernel (raster) or strided copies
+ * (state) and return without waiting, so the outputs are complete once the
+ * stream has reached them (sn_synchronize, or the caller's own event wait on
+ * that stream).  A spike-exchange time-out of an earlier run is reported by
+ * the next synchronising call (sn_synchronize, sn_read_raster,
+ * sn_read_state), not by these.  Errors: SN_EINVAL (NULL out with
+ * n_steps > 0), SN_ERANGE (steps not simulated), SN_ESTATE (another device
+ * current), SN_EDEVICE. */
+sn_status sn_read_raster_device(sn_net* net, int32_t t0, int32_t n_steps, uint32_t* out);
+sn_status sn_read_state_device(sn_net* net, float* V, uint8_t* refractory_left);
+
 /* Returns to the initial state (t = 0, V = r, counters 0, history cleared);
  * synapses and external spikes are kept.  Asynchronous on the stream. */
 sn_status sn_reset_state(sn_net* net);

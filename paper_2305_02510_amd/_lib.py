@@ -20,6 +20,7 @@ EXPORTS = [
     "sn_create_network", "sn_load_weights_delays", "sn_load_dense_weights", "sn_load_dense_rows_i8",
     "sn_set_input_spikes",
     "sn_set_input_spikes_device", "sn_run", "sn_synchronize", "sn_read_raster", "sn_read_state",
+    "sn_read_raster_device", "sn_read_state_device",
     "sn_reset_state", "sn_set_path", "sn_set_slices", "sn_autotune", "sn_get_progress", "sn_destroy_network",
     "sn_last_error", "sn_set_stdp", "sn_read_weights",
     "sn_batch_create", "sn_batch_run", "sn_batch_destroy", "sn_batch_autotune",
@@ -80,6 +81,8 @@ def load():
         "sn_synchronize": [P],
         "sn_read_raster": [P, I32, I32, P],
         "sn_read_state": [P, P, P],
+        "sn_read_raster_device": [P, I32, I32, P],
+        "sn_read_state_device": [P, P, P],
         "sn_reset_state": [P],
         "sn_set_path": [P, I32],
         "sn_set_slices": [P, I32],

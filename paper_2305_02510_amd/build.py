@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsnmi.so")
-SOURCES = ["kernels.hip", "wide.hip", "dense.hip", "rows.hip", "push.hip", "bptt.hip", "layout.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "wide.hip", "readback.hip", "dense.hip", "rows.hip", "push.hip", "bptt.hip", "layout.cpp", "capi.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1307,6 +1307,32 @@ sn_status sn_read_state(sn_net* n, float* V, uint8_t* refractory_left) {
   return SN_OK;
 }
 
+sn_status sn_read_raster_device(sn_net* n, int32_t t0, int32_t n_steps, uint32_t* out) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (n_steps > 0 && !out) return fail(SN_EINVAL, "out must not be NULL");
+  if (t0 < 0 || n_steps < 0 || static_cast<int64_t>(t0) + n_steps > n->t)
+    return fail(SN_ERANGE, "steps [%d, %lld) not simulated (t = %d)", t0, (long long)t0 + n_steps, n->t);
+  if (n_steps == 0) return SN_OK;
+  if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
+  SN_HIP(n, launch_unpack_raster(n->d, t0, n_steps, out, n->stream));
+  return SN_OK;
+}
+
+sn_status sn_read_state_device(sn_net* n, float* V, uint8_t* refractory_left) {
+  sn_status st = check_usable(n);
+  if (st != SN_OK) return st;
+  if (!on_device_ok(n)) return fail(SN_ESTATE, "the network belongs to device %d", n->device);
+  const size_t B = n->d.B, N = n->d.N, Npad = n->d.Npad;
+  // rows of Npad on the device, rows of N in the caller's buffers
+  if (V)
+    SN_HIP(n, hipMemcpy2DAsync(V, N * sizeof(float), n->d.V, Npad * sizeof(float), N * sizeof(float), B,
+                               hipMemcpyDeviceToDevice, n->stream));
+  if (refractory_left)
+    SN_HIP(n, hipMemcpy2DAsync(refractory_left, N, n->d.ref, Npad, N, B, hipMemcpyDeviceToDevice, n->stream));
+  return SN_OK;
+}
+
 sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;

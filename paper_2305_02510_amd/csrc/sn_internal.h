@@ -317,5 +317,6 @@ size_t dense_lds_bytes(int32_t kpad);
 hipError_t launch_reset_state(const DevNet& n, hipStream_t s);
 hipError_t launch_repack_input(const DevNet& n, int32_t t0, int32_t steps, const uint32_t* bits,
                                hipStream_t s);
+hipError_t launch_unpack_raster(const DevNet& n, int32_t t0, int32_t steps, uint32_t* out, hipStream_t s);
 
 }  // namespace snmi

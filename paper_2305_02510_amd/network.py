@@ -166,7 +166,8 @@ class Network:
 
     def set_input_spikes_device(self, t0: int, words) -> None:
         """words: torch int32/uint32 tensor on the device, [B][steps][ceil(N/32)]."""
-        assert words.is_cuda and words.is_contiguous() and words.dim() == 3
+        assert words.is_cuda and words.is_contiguous() and words.dim() == 3 and words.element_size() == 4
+        assert words.shape[0] == self.trials and words.shape[2] == (self.n + 31) // 32
         check(self.lib.sn_set_input_spikes_device(self.h, int(t0), int(words.shape[1]), words.data_ptr()))
 
     # -- running -----------------------------------------------------------
@@ -234,6 +235,25 @@ class Network:
         ref = np.zeros((self.trials, self.n), np.uint8)
         check(self.lib.sn_read_state(self.h, V.ctypes.data, ref.ctypes.data))
         return V, ref
+
+    def read_raster_device(self, t0: int, out) -> None:
+        """Spike words of steps t0 .. t0 + out.shape[1] - 1 into ``out``, a
+        contiguous 4-byte integer tensor [B][steps][ceil(N/32)] on the
+        network's device; asynchronous on the network's stream
+        (sn_read_raster_device)."""
+        assert out.is_cuda and out.is_contiguous() and out.dim() == 3 and out.element_size() == 4
+        assert out.shape[0] == self.trials and out.shape[2] == (self.n + 31) // 32
+        check(self.lib.sn_read_raster_device(self.h, int(t0), int(out.shape[1]), out.data_ptr()))
+
+    def read_state_device(self, V=None, ref=None) -> None:
+        """State into device tensors: V float32 [B][N], ref uint8 [B][N]
+        (either may be None); asynchronous (sn_read_state_device)."""
+        for x, dt in ((V, "torch.float32"), (ref, "torch.uint8")):
+            if x is not None:
+                assert x.is_cuda and x.is_contiguous() and str(x.dtype) == dt
+                assert tuple(x.shape) == (self.trials, self.n)
+        check(self.lib.sn_read_state_device(self.h, V.data_ptr() if V is not None else None,
+                                            ref.data_ptr() if ref is not None else None))
 
     def close(self):
         if getattr(self, "h", None):
