@@ -167,7 +167,6 @@ def bench_single(args, net, kind):
     raster = g.read_raster(0, T)
     V, ref = g.read_state()
     path = g.progress[1]
-    g_recs = net.nnz
     g.close()
     ev = events_of(raster, net.out_degree())
     out = {"value": ev / (ms / 1e3), "ms_per_step": ms, "wall": wall, "events_per_run": ev,
@@ -215,7 +214,6 @@ def bench_single(args, net, kind):
             "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3)}
         out["roofline"]["achieved_counts"] = ("algorithmic bytes: 8 B per synaptic event + 10 B of state per neuron "
                                               "and trial, per time step")
-        out["roofline"]["streamed_record_GBps"] = round(8.0 * g_recs / sec_per_tstep / 1e9, 1) if g_recs else None
         if traffic:
             out["roofline"]["traffic_note"] = (f"HBM bytes per launch of {traffic['time_steps_per_launch']} time steps "
                                                f"(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; {traffic['source']})")
@@ -441,8 +439,7 @@ def bench_batch(args, steps=None, warmup=None):
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic["bytes_per_launch"] if traffic else None,
         "kernel": "k_batch", "bytes_per_time_step": round(bytes_step), "us_per_time_step": round(sec_per_tstep * 1e6, 3),
-        "achieved_counts": "algorithmic bytes: 8 B per synaptic event + 10 B of state per neuron, per time step",
-        "streamed_record_GBps": round(8.0 * nnz / sec_per_tstep / 1e9, 1)}
+        "achieved_counts": "algorithmic bytes: 8 B per synaptic event + 10 B of state per neuron, per time step"}
     if traffic:
         out["roofline"]["traffic_note"] = (f"HBM bytes per launch of {traffic['time_steps_per_launch']} time steps "
                                            f"(rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; {traffic['source']})")

@@ -860,6 +860,7 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   // nets too wide for the per-group kernel's LDS history get their delay >= 2
   // records ordered by delay phase for the wide kernel (wide.hip)
   int32_t phase_rows = 0;
+  bool staged_all = false;  // every delay's history row staged in LDS by the wide kernel
   if (wide_net(n->d)) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, n->device) != hipSuccess) {
@@ -868,6 +869,7 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     }
     const WidePlan wp = wide_plan(n->d, cus);
     if (wp.P > 1) phase_rows = wp.Dl;
+    staged_all = wp.P > 1 || (wp.Dl >= n->d.D && wp.Dl > 0);
   }
   HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows);
   if (L.too_large)
@@ -876,16 +878,18 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
   float cscale = 0.f;
   const std::vector<uint32_t> C = compact_records(L, n->d.N, n->d.D, &cscale);
-  // wide nets: a lane-only copy of the layout as 4-byte lane records, kept
-  // when it is at most 80% of the 8-byte records' bytes
+  // wide nets with every delay staged: a lane-only copy of the layout as
+  // 4-byte lane records, kept when it is at most 80% of the 8-byte records'
+  // bytes
   std::vector<uint32_t> LR;
   std::vector<int32_t> lgp, lws;
   float lscale = 0.f;
-  if (wide_net(n->d) && n->d.N <= kLaneRecMaxNeurons && nnz > 0) {
+  if (staged_all && nnz > 0) {
     HostLayout LL = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows, true);
     if (!LL.too_large && LL.phases == L.phases && 4.0 * LL.recs.size() <= 0.8 * 8.0 * L.recs.size()) {
-      LR = lane_records(LL, n->d.N, &lscale);
+      LR = lane_records(LL, n->d.G, &lscale);
       if (!LR.empty()) {
+        LR.resize(LR.size() + static_cast<size_t>(kLaneBatchRows) * kGroup, 0u);  // slack of one batch
         lgp = std::move(LL.gptr);
         lws = std::move(LL.wsec);
       }

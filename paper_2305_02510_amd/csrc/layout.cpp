@@ -165,20 +165,25 @@ std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t ma
   return out;
 }
 
-std::vector<uint32_t> lane_records(const HostLayout& L, int32_t n, float* scale) {
+std::vector<uint32_t> lane_records(const HostLayout& L, int32_t G, float* scale) {
   std::vector<uint32_t> out;
-  if (n > kLaneRecMaxNeurons || L.recs.empty()) return out;
+  if (L.recs.empty()) return out;
   std::vector<float> w(L.recs.size());
   for (size_t i = 0; i < w.size(); ++i) w[i] = L.recs[i].w;
   const int32_t e = int8_exponent(w.data(), static_cast<int64_t>(w.size()));
   if (e < 0) return out;
   const float f = std::ldexp(1.f, e);
+  const uint32_t W32 = 2u * static_cast<uint32_t>(G);
   out.resize(L.recs.size());
   for (size_t i = 0; i < out.size(); ++i) {
     const Rec& r = L.recs[i];
     if ((r.meta >> 26) != static_cast<uint32_t>(i % kGroup)) return {};  // not lane-owned
     const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
-    out[i] = lane_record(k, r.meta & 0xFFFFFu, ((r.meta >> 20) & 63u) + 1u);
+    const uint32_t pre = r.meta & 0xFFFFFu, d1 = (r.meta >> 20) & 63u;  // d1 = delay - 1
+    const uint32_t row = L.phase_rows > 0 ? d1 % static_cast<uint32_t>(L.phase_rows) : d1;
+    const uint64_t offset = (static_cast<uint64_t>(row) * W32 + (pre >> 5)) * 4u;
+    if (offset >= kLaneMaxOffset) return {};
+    out[i] = lane_record(k, static_cast<uint32_t>(offset), pre & 31u);
   }
   *scale = std::ldexp(1.f, -e);
   return out;

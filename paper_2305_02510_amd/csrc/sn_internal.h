@@ -78,16 +78,27 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
                         const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0, bool lane_only = false);
 
-// Lane record, 4 bytes, of a lane_only layout (the post is the lane), for
-// the wide per-step kernel, nets with N <= 2^18 and every weight k * 2^-e
-// with |k| <= 127:  bits 0..7 k (int8), bits 8..13 delay - 1, bits 14..31 pre.
-constexpr int32_t kLaneRecMaxNeurons = 1 << 18;
-__host__ __device__ inline uint32_t lane_record(int32_t k, uint32_t pre, uint32_t delay) {
-  return (static_cast<uint32_t>(k) & 0xFFu) | ((delay - 1u) << 8) | (pre << 14);
+// Lane record, 4 bytes, of a lane_only layout (the post is the lane) for the
+// wide per-step kernel when every delay is staged in LDS, nets whose weights
+// are all k * 2^-e with |k| <= 127:
+//   bits 0..4    the source's bit in its 32-bit history word (pre mod 32)
+//   bits 5..22   LDS byte offset of that word among the phase's staged rows,
+//                (((delay - 1) mod phase_rows) * 2G + pre / 32) * 4
+//   bits 24..31  k (int8)
+// A filler has k = 0.  The kernel reads batches of kLaneBatchRows rows and
+// skips the rows of a batch past its section's end (sections are whole
+// rows), so the device array carries one batch of zero records of slack
+// after the last section.
+constexpr int32_t kLaneBatchRows = 8;
+constexpr uint32_t kLaneMaxOffset = 1u << 18;
+__host__ __device__ inline uint32_t lane_record(int32_t k, uint32_t byte_offset, uint32_t bit) {
+  return (static_cast<uint32_t>(k) << 24) | (byte_offset << 5) | bit;
 }
-// 4-byte copies of a lane_only layout's records, or empty when a record is
-// not in its post's lane or a weight does not allow it; *scale = 2^-e.
-std::vector<uint32_t> lane_records(const HostLayout& L, int32_t n, float* scale);
+// Lane records of a lane_only layout for G groups and the layout's phases
+// (phase_rows = 0: no phases, every delay staged at once), or empty when a
+// record is not in its post's lane, a weight does not allow it or an offset
+// does not fit; *scale = 2^-e.
+std::vector<uint32_t> lane_records(const HostLayout& L, int32_t G, float* scale);
 
 // Plain pointers and sizes handed to every kernel.
 struct DevNet {

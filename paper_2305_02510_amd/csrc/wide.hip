@@ -28,10 +28,14 @@
 // barrier.  After the last phase wave w updates groups g0 + w, g0 + w + 16,
 // ... and writes their spike words.
 //
-// LANE: the net also holds a lane-only copy of its layout (no overflow: every
-// record in its post's lane) as 4-byte lane records (int8 weight numerator,
-// delay, pre-neuron); the kernel then streams those, half the bytes of the
-// 8-byte records, with no atomic at all.
+// LANE: when every delay is staged (phases cover D) the net may also hold a
+// lane-only copy of its layout (no overflow: every record in its post's lane)
+// as 4-byte lane records that carry the LDS offset of their source word, the
+// source's bit and an int8 weight numerator, with every section padded to
+// whole batches.  The kernel then streams those, half the bytes of the
+// 8-byte records, with no atomic, no bounds mask and no address arithmetic
+// beyond two bit-field extractions per record; a lane sums its numerators as
+// an integer and scales the sum once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,42 +47,26 @@ namespace snmi {
 
 constexpr int kWideThreads = 1024;
 constexpr int kWideWaves = kWideThreads / 64;
-// records per lane in one batch: 8 records of 8 bytes or 8 lane records
-// (lane records on the N = 100,000, p = 0.01 net: 8 -> 112 us per step, 12 ->
-// 113, 16 -> 125, 24 -> 291)
-template <bool LANE>
-constexpr int kWideU = 8;
-template <bool LANE>
-struct WideRec {
-  using type = Rec;
-};
-template <>
-struct WideRec<true> {
-  using type = uint32_t;
-};
+constexpr int kWideU = 8;                              // 8-byte records per lane in one batch
 constexpr int kWideNpw = 4;                            // groups updated per wave, at most
 constexpr int kWideStage = 8;                          // history words per thread in flight while staging
-constexpr size_t kWideStaticLds = kWideWaves * kGroup * sizeof(float) + 64;
+constexpr size_t kWidePartLds = kWideWaves * kGroup * sizeof(float);  // a team's per-wave sums
+constexpr size_t kWideStaticLds = 64;
 constexpr size_t kWideLdsLimit = 160 * 1024;
 constexpr size_t kStepRingLimitWide = 64 * 1024;  // below this the per-group kernel stages every row
 
 // Loads are unconditional, from an index clamped into [0, end) (the records
 // array always holds at least one record's worth of memory), so all of them
 // stay in flight together; records past `end` are masked when delivered.
-template <bool LANE>
-__device__ __forceinline__ void wide_load(const DevNet& n, int base, int end, int lane,
-                                          typename WideRec<LANE>::type (&r)[kWideU<LANE>]) {
+__device__ __forceinline__ void wide_load(const DevNet& n, int base, int end, int lane, Rec (&r)[kWideU]) {
 #pragma unroll
-  for (int u = 0; u < kWideU<LANE>; ++u) {
-    const int k = max(0, min(base + u * 64 + lane, end - 1));
-    if constexpr (LANE) r[u] = n.lrecs[k];
-    else r[u] = n.recs[k];
-  }
+  for (int u = 0; u < kWideU; ++u) r[u] = n.recs[max(0, min(base + u * 64 + lane, end - 1))];
 }
 
 // Records of group g in phase p: phase p >= 1 is the section [wsec[p],
 // wsec[p - 1]); phase 0 runs from wsec[0] to the group's end (delay-1 part
-// included).  Without phases: all records of the group.
+// included).  Without phases: all records of the group.  LANE: the offsets of
+// the lane-record layout.
 template <bool LANE>
 __device__ __forceinline__ void wide_range(const DevNet& n, int g, int p, int& beg, int& end) {
   const int32_t* gp = LANE ? n.lgptr : n.gptr;
@@ -101,14 +89,12 @@ struct WidePair {
   bool valid;
 };
 
-template <bool LANE>
 __device__ __forceinline__ void wide_enter(const DevNet& n, WidePair& s, int p) {
-  constexpr int batch = 64 * kWideU<LANE>;
-  wide_range<LANE>(n, s.g, p, s.beg, s.end);
+  constexpr int batch = 64 * kWideU;
+  wide_range<false>(n, s.g, p, s.beg, s.end);
   s.nb = max(1, (s.end - s.beg + batch - 1) / batch);
 }
 
-template <bool LANE>
 __device__ __forceinline__ WidePair wide_start(const DevNet& n, int p, int g0, int g1, bool own, int team,
                                                int member) {
   WidePair s{};
@@ -116,13 +102,12 @@ __device__ __forceinline__ WidePair wide_start(const DevNet& n, int p, int g0, i
   s.k = own ? 0 : member;
   s.valid = s.g < g1;
   if (s.valid) {
-    wide_enter<LANE>(n, s, p);
+    wide_enter(n, s, p);
     s.valid = s.k < s.nb;
   }
   return s;
 }
 
-template <bool LANE>
 __device__ __forceinline__ WidePair wide_next(const DevNet& n, const WidePair& s, int p, int g1, int m, bool own) {
   WidePair r = s;
   if (!s.valid) return r;
@@ -133,37 +118,98 @@ __device__ __forceinline__ WidePair wide_next(const DevNet& n, const WidePair& s
       r.g = s.g + kWideWaves;
       r.k = 0;
       r.valid = r.g < g1;
-      if (r.valid) wide_enter<LANE>(n, r, p);
+      if (r.valid) wide_enter(n, r, p);
     }
   }
   return r;
 }
 
-template <bool LANE>
-__device__ __forceinline__ int wide_first(const WidePair& s) { return s.beg + s.k * (64 * kWideU<LANE>); }
+__device__ __forceinline__ int wide_first(const WidePair& s) { return s.beg + s.k * (64 * kWideU); }
 
 // A pair past the wave's last one loads (and never delivers) that last
 // pair's records again.
-template <bool LANE>
-__device__ __forceinline__ void wide_load_pair(const DevNet& n, const WidePair& s, int lane,
-                                               typename WideRec<LANE>::type (&r)[kWideU<LANE>]) {
-  wide_load<LANE>(n, wide_first<LANE>(s), s.end, lane, r);
+__device__ __forceinline__ void wide_load_pair(const DevNet& n, const WidePair& s, int lane, Rec (&r)[kWideU]) {
+  wide_load(n, wide_first(s), s.end, lane, r);
+}
+
+// Lane-record walk: a pair is (group, batch) as above; sections are whole
+// rows, so a batch that runs past its section's end skips the rows beyond it
+// (a uniform test per row, no per-record mask), and empty sections are
+// skipped.  Loads past a section's end stay inside the array's slack.
+constexpr int kLaneU = kLaneBatchRows;  // records per lane in one batch
+struct LanePair {
+  int g, k, beg, end, nb;
+  bool valid;
+};
+
+__device__ __forceinline__ void lane_enter(const DevNet& n, LanePair& s, int p) {
+  wide_range<true>(n, s.g, p, s.beg, s.end);
+  s.nb = (s.end - s.beg + 64 * kLaneU - 1) / (64 * kLaneU);
+}
+
+// From s.g: an owning wave moves on to its first group (every 16th) with a
+// non-empty section; a team member keeps its group if its batch exists.
+__device__ __forceinline__ void lane_settle(const DevNet& n, LanePair& s, int p, int g1, bool own) {
+  s.valid = s.g < g1;
+  if (!s.valid) return;
+  lane_enter(n, s, p);
+  if (own) {
+    while (s.nb == 0) {
+      s.g += kWideWaves;
+      if (s.g >= g1) {
+        s.valid = false;
+        return;
+      }
+      lane_enter(n, s, p);
+    }
+  }
+  s.valid = s.k < s.nb;
+}
+
+__device__ __forceinline__ LanePair lane_start(const DevNet& n, int p, int g0, int g1, bool own, int team,
+                                               int member) {
+  LanePair s{};
+  s.g = g0 + team;
+  s.k = own ? 0 : member;
+  lane_settle(n, s, p, g1, own);
+  return s;
+}
+
+__device__ __forceinline__ LanePair lane_next(const DevNet& n, const LanePair& s, int p, int g1, int m, bool own) {
+  LanePair r = s;
+  if (!s.valid) return r;
+  r.k = s.k + m;
+  if (r.k >= s.nb) {
+    r.valid = false;
+    if (own) {
+      r.g = s.g + kWideWaves;
+      r.k = 0;
+      lane_settle(n, r, p, g1, true);
+    }
+  }
+  return r;
+}
+
+// A pair past the wave's last one loads the array's first batch (never
+// delivered); the array holds at least one batch (its slack).
+__device__ __forceinline__ void lane_load(const DevNet& n, const LanePair& s, int lane, uint32_t (&r)[kLaneU]) {
+  const uint32_t* src = n.lrecs + (s.valid ? s.beg + s.k * (64 * kLaneU) : 0) + lane;
+#pragma unroll
+  for (int u = 0; u < kLaneU; ++u) r[u] = src[u * 64];
 }
 
 // FALLBACK: no delay phases and more delays than staged rows; delays above
 // the staged rows read the raster in memory.
 // NPW: groups one wave updates at most (1 when a workgroup has <= 16).
-// LANE: lane records (n.lrecs, n.lgptr, n.lwsec).
+// LANE: lane records (n.lrecs, n.lgptr, n.lwsec); never with FALLBACK.
 template <bool FALLBACK, int NPW, bool LANE>
 __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int t, int Dl, int P) {
-  constexpr int U = kWideU<LANE>;
-  using Held = typename WideRec<LANE>::type;
+  constexpr int U = kWideU;
   extern __shared__ __align__(16) uint32_t smem[];
-  __shared__ float part[kWideWaves][kGroup];
   const int b = blockIdx.y;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the walk state lives in scalars
   const int W32 = 2 * n.G;
   const size_t rstride = static_cast<size_t>(n.B) * n.G;
   const uint64_t* hist = n.raster + static_cast<size_t>(b) * n.G;
@@ -177,8 +223,11 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
   const int tfirst = own ? wave : (team * kWideWaves + ng - 1) / ng;
   const int m = own ? 1 : (team + 1 == ng ? kWideWaves : ((team + 1) * kWideWaves + ng - 1) / ng) - tfirst;
   const int member = wave - tfirst;
+  // LDS: the staged rows first (a lane record's offset is an LDS address),
+  // then the groups' sums and the team slots
   uint32_t* ring = smem;                                              // [Dl][W32]
   float* gacc = reinterpret_cast<float*>(smem + static_cast<size_t>(Dl) * W32);  // [g1 - g0][64]
+  float(*part)[kGroup] = reinterpret_cast<float(*)[kGroup]>(gacc + static_cast<size_t>(ng) * kGroup);  // [16][64]
 
   // neuron state of the groups this wave updates, loaded now, used last
   float V[NPW], th[NPW], lam[NPW], rs[NPW], amp[NPW];
@@ -231,55 +280,96 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
     }
     __syncthreads();
 
-    // this wave's (group, batch) walk: no barrier until the phase ends, three
-    // record buffers in rotation keep two batches in flight while one is
-    // delivered (no buffer is copied: a copy would wait for its load)
-    WidePair s0 = wide_start<LANE>(n, p, g0, g1, own, team, member);
-    WidePair s1 = wide_next<LANE>(n, s0, p, g1, m, own), s2 = wide_next<LANE>(n, s1, p, g1, m, own);
-    Held b0[U], b1[U], b2[U];
-    wide_load_pair<LANE>(n, s0, lane, b0);
-    wide_load_pair<LANE>(n, s1, lane, b1);
-    wide_load_pair<LANE>(n, s2, lane, b2);
-    float sum = 0.f;
-    // delivers the batch of pair sc; an owned group's sum is added to its row
-    // when the walk leaves it; false when sc was the wave's last pair
-    auto body = [&](const WidePair& sc, const Held (&cur)[U], const WidePair& sn) -> bool {
-      if (!sc.valid) return false;
-      float* acc_g = gacc + (sc.g - g0) * kGroup;
-      const int first = wide_first<LANE>(sc) + lane;
-      uint32_t bit[U];
+    float tsum = 0.f;  // a team member's share of its group's sums
+    if constexpr (LANE) {
+      // this wave's (group, batch) walk: no barrier until the phase ends,
+      // three record buffers in rotation keep two batches in flight while one
+      // is delivered (no buffer is copied: a copy would wait for its load)
+      LanePair s0 = lane_start(n, p, g0, g1, own, team, member);
+      LanePair s1 = lane_next(n, s0, p, g1, m, own), s2 = lane_next(n, s1, p, g1, m, own);
+      uint32_t b0[kLaneU], b1[kLaneU], b2[kLaneU];
+      lane_load(n, s0, lane, b0);
+      lane_load(n, s1, lane, b1);
+      lane_load(n, s2, lane, b2);
+      const char* ring_bytes = reinterpret_cast<const char*>(ring);
+      int isum = 0;  // sum of the weight numerators k of this lane's active records
+      auto body = [&](const LanePair& sc, const uint32_t (&cur)[kLaneU], const LanePair& sn) -> bool {
+        if (!sc.valid) return false;
+        auto deliver = [&](uint32_t c) {
+          const uint32_t word = *reinterpret_cast<const uint32_t*>(ring_bytes + ((c >> 5) & (kLaneMaxOffset - 1u)));
+          // all ones when the source spiked (the bit sign-extended), else 0
+          // (v_bfe reads only the offset's low 5 bits: the source's bit)
+          const int active = __builtin_amdgcn_sbfe(static_cast<int>(word), c, 1u);
+          isum += active & (static_cast<int>(c) >> 24);
+        };
+        const int rows_left = (sc.end - sc.beg) / 64 - sc.k * kLaneU;  // uniform
+        if (rows_left >= kLaneU) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        int d;
-        uint32_t pre;
-        if constexpr (LANE) {
-          d = static_cast<int>((cur[u] >> 8) & 63u) + 1;
-          pre = cur[u] >> 14;
-        } else {
-          d = static_cast<int>((cur[u].meta >> 20) & 63u) + 1;
-          pre = cur[u].meta & 0xFFFFFu;
+          for (int u = 0; u < kLaneU; ++u) deliver(cur[u]);
+        } else {  // the section's last batch
+#pragma unroll
+          for (int u = 0; u < kLaneU; ++u)
+            if (u < rows_left) deliver(cur[u]);
         }
-        const bool valid = first + u * 64 < sc.end;
-        const int r = d - dbase - 1;  // row of the phase's staged rows
-        if (!FALLBACK) {
-          // every record of the phase lies in its rows; a masked one may not
-          const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), rows - 1));
-          bit[u] = (ring[__umul24(rc, static_cast<uint32_t>(W32)) + (pre >> 5)] >> (pre & 31u)) &
-                   static_cast<uint32_t>(valid);
-        } else if (r < rows) {
-          bit[u] = (ring[__umul24(static_cast<uint32_t>(r), static_cast<uint32_t>(W32)) + (pre >> 5)] >> (pre & 31u)) &
-                   static_cast<uint32_t>(valid);
-        } else {  // a delay beyond the staged rows
-          bit[u] = valid && t - d >= 0
-                       ? static_cast<uint32_t>(hist[static_cast<size_t>(t - d) * rstride + (pre >> 6)] >> (pre & 63u)) & 1u
-                       : 0u;
+        if (own && (!sn.valid || sn.g != sc.g)) {  // an owned group: this wave is its only contributor
+          gacc[(sc.g - g0) * kGroup + lane] += static_cast<float>(isum) * n.lscale;
+          isum = 0;
         }
+        return sn.valid;
+      };
+      for (;;) {
+        if (!body(s0, b0, s1)) break;
+        const LanePair s3 = lane_next(n, s2, p, g1, m, own);
+        lane_load(n, s3, lane, b0);
+        if (!body(s1, b1, s2)) break;
+        const LanePair s4 = lane_next(n, s3, p, g1, m, own);
+        lane_load(n, s4, lane, b1);
+        if (!body(s2, b2, s3)) break;
+        const LanePair s5 = lane_next(n, s4, p, g1, m, own);
+        lane_load(n, s5, lane, b2);
+        s0 = s3;
+        s1 = s4;
+        s2 = s5;
       }
-      if constexpr (LANE) {  // every record is of this lane's post
+      tsum = static_cast<float>(isum) * n.lscale;
+    } else {
+      // this wave's (group, batch) walk: no barrier until the phase ends, three
+      // record buffers in rotation keep two batches in flight while one is
+      // delivered (no buffer is copied: a copy would wait for its load)
+      WidePair s0 = wide_start(n, p, g0, g1, own, team, member);
+      WidePair s1 = wide_next(n, s0, p, g1, m, own), s2 = wide_next(n, s1, p, g1, m, own);
+      Rec b0[U], b1[U], b2[U];
+      wide_load_pair(n, s0, lane, b0);
+      wide_load_pair(n, s1, lane, b1);
+      wide_load_pair(n, s2, lane, b2);
+      float sum = 0.f;
+      // delivers the batch of pair sc; an owned group's sum is added to its
+      // row when the walk leaves it; false when sc was the wave's last pair
+      auto body = [&](const WidePair& sc, const Rec (&cur)[U], const WidePair& sn) -> bool {
+        if (!sc.valid) return false;
+        float* acc_g = gacc + (sc.g - g0) * kGroup;
+        const int first = wide_first(sc) + lane;
+        uint32_t bit[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          sum += bit[u] ? static_cast<float>(static_cast<int8_t>(cur[u] & 0xFFu)) * n.lscale : 0.f;
-      } else {
+        for (int u = 0; u < U; ++u) {
+          const int d = static_cast<int>((cur[u].meta >> 20) & 63u) + 1;
+          const uint32_t pre = cur[u].meta & 0xFFFFFu;
+          const bool valid = first + u * 64 < sc.end;
+          const int r = d - dbase - 1;  // row of the phase's staged rows
+          if (!FALLBACK) {
+            // every record of the phase lies in its rows; a masked one may not
+            const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), rows - 1));
+            bit[u] = (ring[__umul24(rc, static_cast<uint32_t>(W32)) + (pre >> 5)] >> (pre & 31u)) &
+                     static_cast<uint32_t>(valid);
+          } else if (r < rows) {
+            bit[u] = (ring[__umul24(static_cast<uint32_t>(r), static_cast<uint32_t>(W32)) + (pre >> 5)] >> (pre & 31u)) &
+                     static_cast<uint32_t>(valid);
+          } else {  // a delay beyond the staged rows
+            bit[u] = valid && t - d >= 0
+                         ? static_cast<uint32_t>(hist[static_cast<size_t>(t - d) * rstride + (pre >> 6)] >> (pre & 63u)) & 1u
+                         : 0u;
+          }
+        }
         bool other = false;  // an active overflow record of another lane's post
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -294,29 +384,30 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
             if (bit[u] && post != static_cast<uint32_t>(lane)) atomicAdd(&acc_g[post], cur[u].w);
           }
         }
+        if (own && (!sn.valid || sn.g != sc.g)) {  // an owned group: this wave is its only contributor
+          acc_g[lane] += sum;
+          sum = 0.f;
+        }
+        return sn.valid;
+      };
+      for (;;) {
+        if (!body(s0, b0, s1)) break;
+        const WidePair s3 = wide_next(n, s2, p, g1, m, own);
+        wide_load_pair(n, s3, lane, b0);
+        if (!body(s1, b1, s2)) break;
+        const WidePair s4 = wide_next(n, s3, p, g1, m, own);
+        wide_load_pair(n, s4, lane, b1);
+        if (!body(s2, b2, s3)) break;
+        const WidePair s5 = wide_next(n, s4, p, g1, m, own);
+        wide_load_pair(n, s5, lane, b2);
+        s0 = s3;
+        s1 = s4;
+        s2 = s5;
       }
-      if (own && (!sn.valid || sn.g != sc.g)) {  // an owned group: this wave is its only contributor
-        acc_g[lane] += sum;
-        sum = 0.f;
-      }
-      return sn.valid;
-    };
-    for (;;) {
-      if (!body(s0, b0, s1)) break;
-      const WidePair s3 = wide_next<LANE>(n, s2, p, g1, m, own);
-      wide_load_pair<LANE>(n, s3, lane, b0);
-      if (!body(s1, b1, s2)) break;
-      const WidePair s4 = wide_next<LANE>(n, s3, p, g1, m, own);
-      wide_load_pair<LANE>(n, s4, lane, b1);
-      if (!body(s2, b2, s3)) break;
-      const WidePair s5 = wide_next<LANE>(n, s4, p, g1, m, own);
-      wide_load_pair<LANE>(n, s5, lane, b2);
-      s0 = s3;
-      s1 = s4;
-      s2 = s5;
+      tsum = sum;
     }
     if (!own) {  // a team of m waves per group: the sums meet in LDS
-      part[wave][lane] = sum;
+      part[wave][lane] = tsum;
       __syncthreads();
       if (member == 0) {
         float a = gacc[team * kGroup + lane];
@@ -357,7 +448,7 @@ WidePlan wide_plan(const DevNet& n, int cus) {
   }
   const size_t row = static_cast<size_t>(2 * n.G) * sizeof(uint32_t);
   const size_t sums = static_cast<size_t>(w.gpw) * kGroup * sizeof(float);
-  const size_t avail = kWideLdsLimit - kWideStaticLds - sums;
+  const size_t avail = kWideLdsLimit - kWideStaticLds - kWidePartLds - sums;
   w.Dl = static_cast<int>(std::min<size_t>(avail / row, static_cast<size_t>(n.D)));
   w.P = w.Dl > 0 ? (n.D + w.Dl - 1) / w.Dl : 0;
   if (w.P > kWideMaxPhases) w.P = 1;  // too many phases: delays above Dl read memory
@@ -365,7 +456,8 @@ WidePlan wide_plan(const DevNet& n, int cus) {
 }
 
 static size_t wide_lds(const DevNet& n, const WidePlan& w, int Dl) {
-  return static_cast<size_t>(Dl) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(w.gpw) * kGroup * sizeof(float);
+  return static_cast<size_t>(Dl) * 2 * n.G * sizeof(uint32_t) + static_cast<size_t>(w.gpw) * kGroup * sizeof(float) +
+         kWidePartLds;
 }
 
 // Phases come from the layout (n.phases, n.phase_rows); a layout without
@@ -382,9 +474,7 @@ hipError_t prepare_wide_kernel(const DevNet& n, int cus) {
                        reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, false>),
                        reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw, false>),
                        reinterpret_cast<const void*>(&k_step_wide<false, 1, true>),
-                       reinterpret_cast<const void*>(&k_step_wide<true, 1, true>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true>),
-                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw, true>)};
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -401,7 +491,8 @@ hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) 
   const bool fallback = P == 1 && Dl < n.D;
   const dim3 grid(w.grid, n.B), block(kWideThreads);
   const size_t lds = wide_lds(n, w, Dl);
-  const bool lane = n.lrecs != nullptr;
+  // lane records address the staged rows: only when every delay is staged
+  const bool lane = n.lrecs != nullptr && !fallback;
 #define SN_WIDE(FB, NPW, LN) hipLaunchKernelGGL((k_step_wide<FB, NPW, LN>), grid, block, lds, s, n, t, Dl, P)
   const int key = (fallback ? 1 : 0) + (w.gpw <= kWideWaves ? 0 : 2) + (lane ? 4 : 0);
   switch (key) {
@@ -410,9 +501,7 @@ hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) 
     case 2: SN_WIDE(false, kWideNpw, false); break;
     case 3: SN_WIDE(true, kWideNpw, false); break;
     case 4: SN_WIDE(false, 1, true); break;
-    case 5: SN_WIDE(true, 1, true); break;
-    case 6: SN_WIDE(false, kWideNpw, true); break;
-    default: SN_WIDE(true, kWideNpw, true); break;
+    default: SN_WIDE(false, kWideNpw, true); break;
   }
 #undef SN_WIDE
   return hipGetLastError();

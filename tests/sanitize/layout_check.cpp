@@ -129,6 +129,53 @@ static void check_layout(const Net& net, int32_t phase_rows) {
   }
 }
 
+// The lane-only layout of the wide kernel and its 4-byte lane records: every
+// section whole rows, every record in its post's lane, and each lane record
+// naming the LDS word and bit of its source in the phase's staged rows, with
+// its weight's numerator (fillers: k = 0).
+static void check_lane_layout(const Net& net, int32_t phase_rows) {
+  const int64_t nnz = static_cast<int64_t>(net.pre.size());
+  HostLayout L = build_layout(net.n, nnz, net.pre.data(), net.post.data(), net.w.data(), net.d.data(), net.D,
+                              phase_rows, true);
+  CHECK(!L.too_large, "lane layout: unexpected too_large");
+  const int32_t G = (net.n + kGroup - 1) / kGroup;
+  const int32_t P = L.phases;
+  float scale = 0.f;
+  const std::vector<uint32_t> LR = lane_records(L, G, &scale);
+  if (nnz == 0) return;
+  CHECK(LR.size() == L.recs.size(), "lane records missing (%zu of %zu)", LR.size(), L.recs.size());
+  const int64_t row = kGroup;
+  std::vector<int> seen(static_cast<size_t>(nnz), 0);
+  for (int32_t g = 0; g < G; ++g) {
+    // sections: phases P-1 .. 0 of the delay >= 2 records, then the delay-1 records
+    std::vector<int32_t> bound;
+    for (int32_t p = P - 1; p >= 0; --p) bound.push_back(L.wsec[static_cast<size_t>(g) * P + p]);
+    bound.push_back(L.gsplit[g]);
+    bound.push_back(L.gptr[g + 1]);
+    CHECK(bound[0] == L.gptr[g], "lane group %d: first section", g);
+    for (size_t q = 0; q + 1 < bound.size(); ++q)
+      CHECK(bound[q] <= bound[q + 1] && (bound[q + 1] - bound[q]) % row == 0, "lane group %d: section %zu", g, q);
+    for (int32_t i = L.gptr[g]; i < L.gptr[g + 1]; ++i) {
+      const uint32_t c = LR[i];
+      const int32_t k = L.src[i];
+      CHECK(static_cast<int32_t>(L.recs[i].meta >> 26) == (i - L.gptr[g]) % kGroup, "lane record %d off its lane", i);
+      if (k < 0) {
+        CHECK((c >> 24) == 0, "filler %d: k", i);
+        continue;
+      }
+      ++seen[k];
+      const int32_t pre = net.pre[k], d = net.d[k];
+      const uint32_t row = P > 1 ? static_cast<uint32_t>((d - 1) % phase_rows) : static_cast<uint32_t>(d - 1);
+      const uint32_t off = (c >> 5) & (kLaneMaxOffset - 1u);
+      CHECK(off % 4 == 0 && off / 4 == row * 2u * G + static_cast<uint32_t>(pre) / 32u, "lane record %d: offset", i);
+      CHECK((c & 31u) == static_cast<uint32_t>(pre) % 32u, "lane record %d: bit", i);
+      const float wk = static_cast<float>(static_cast<int8_t>(c >> 24)) * scale;
+      CHECK(wk == net.w[k], "lane record %d: weight", i);
+    }
+  }
+  for (int64_t k = 0; k < nnz; ++k) CHECK(seen[k] == 1, "lane layout: synapse %lld seen %d times", (long long)k, seen[k]);
+}
+
 static Net random_net(uint32_t seed, int32_t n, double p, int32_t D, bool dups_and_loops) {
   std::mt19937 rng(seed);
   Net net;
@@ -158,6 +205,9 @@ int main() {
   auto run = [&](const Net& net) {
     for (int32_t pr : {0, 1, 3, 7, 31}) {
       check_layout(net, pr);
+      if (g_fail) return;
+      ++cases;
+      check_lane_layout(net, pr);
       if (g_fail) return;
       ++cases;
     }

@@ -190,6 +190,34 @@ def test_wide_step_delay_phases(gpu, oracle, n, p, D, trials):
     assert_parity(net, res, s, V, r, f"wide step n={n} D={D} trials={trials}")
 
 
+def _with_gaps(net):
+    """The same net with empty record sections: no synapse into the groups
+    g = 3 mod 7, no delay-1 synapse into g = 1 mod 5, none of delay 2..4
+    into g = 2 mod 3."""
+    g = net.post // 64
+    d = net.delay
+    keep = (g % 7 != 3) & ~((g % 5 == 1) & (d == 1)) & ~((g % 3 == 2) & (d >= 2) & (d <= 4))
+    return dataclasses.replace(net, pre=net.pre[keep], post=net.post[keep], weight=net.weight[keep],
+                               delay=net.delay[keep], name=net.name + "_gaps")
+
+
+@pytest.mark.parametrize("n,p,D,trials", [(20_000, 0.002, 64, 2), (33_000, 0.001, 20, 1), (270_000, 0.0001, 8, 1)])
+def test_wide_step_lane_records(gpu, oracle, n, p, D, trials):
+    """The wide per-step kernel on 4-byte lane records (every post's synapses
+    in its lane, no hub: the lane-only copy is kept): two delay phases with
+    2 trials; every delay staged at once; more than 16 groups per workgroup
+    (each wave owns groups) with two phases; empty sections throughout."""
+    net = wl.large_sparse(60 + D, n=n, p=p, steps=90, max_delay=D)
+    net = _with_gaps(dataclasses.replace(net, trials=trials, ext=np.concatenate([net.ext] * trials)))
+    if trials > 1:
+        net.ext[1] = np.roll(net.ext[1], 5, axis=0)
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "step", chunks=[1, 40, 49])
+    assert used == "step"
+    assert_parity(net, res, s, V, r, f"lane records n={n} D={D} trials={trials}")
+    assert 0.002 < s.mean() < 0.6, s.mean()
+
+
 def test_large_sparse_low_rate(gpu, oracle):
     net = wl.large_sparse_low(2, steps=300)
     res = oracle.run_sparse(net)
