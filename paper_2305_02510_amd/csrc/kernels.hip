@@ -74,10 +74,9 @@ __host__ __device__ __forceinline__ int acc_rows(int ng_max, int nwave) {
 // valid[u] is false past `end`.  Loads are issued unconditionally with the
 // index clamped into the chunk (start < end), so the four are in flight
 // together; deliver_chunk masks the invalid ones.  COMPACT reads the 4-byte
-// copies of the records (n.crecs) and expands them to weight and meta word.
+// copies of the records (n.crecs, see compact_record).
 // A record as held between its load and its delivery: the 8-byte record,
-// or with COMPACT its 4-byte copy, expanded only when delivered (a chunk in
-// flight then costs half the registers).
+// or with COMPACT its 4-byte copy.
 template <bool COMPACT>
 struct RecHeld {
   using type = Rec;
@@ -101,19 +100,6 @@ __device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int 
       rc[u] = lrec[kc - r0];
     } else {
       rc[u] = n.recs[kc];
-    }
-  }
-}
-
-template <bool COMPACT, int U = 4>
-__device__ __forceinline__ void expand_recs(const DevNet& n, const typename RecHeld<COMPACT>::type (&held)[U],
-                                            Rec (&rc)[U]) {
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if constexpr (COMPACT) {
-      rc[u] = expand_compact(held[u], n.cscale);
-    } else {
-      rc[u] = held[u];
     }
   }
 }
@@ -183,6 +169,68 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U
   }
 }
 
+// The U compact records of one chunk held by a lane (batch kernel: ring in
+// LDS, records streamed from memory).  A record carries its source word's
+// offset from the current ring row, so the lookup is one add and a wrap,
+// and its source bit, extracted sign-extended into an all-ones mask.  The
+// numerators k of active own-post records are summed as an integer (exact;
+// scaled once when the sum is flushed), other posts' weights are added
+// atomically.
+template <int U>
+__device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const bool (&valid)[U], const uint32_t* ring,
+                                                float* acc_g, int& isum, float scale, int lane, uint32_t curW,
+                                                uint32_t DrW) {
+  int act[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t c = rc[u];
+    uint32_t adr = curW + ((c >> 5) & (kCompactMaxRing - 1u));
+    adr = min(adr, adr - DrW);  // the row of step t - d: cur - d modulo Dr
+    // (v_bfe reads only the offset's low 5 bits: the source's bit)
+    act[u] = __builtin_amdgcn_sbfe(static_cast<int>(ring[adr]), c, 1u) & -static_cast<int>(valid[u]);
+  }
+  bool other = false;  // an active overflow record of another lane's post (rare)
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool own = ((rc[u] >> 18) & 63u) == static_cast<uint32_t>(lane);
+    isum += (own ? act[u] : 0) & (static_cast<int>(rc[u]) >> 24);
+    other |= act[u] != 0 && !own;
+  }
+  if (other) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t post = (rc[u] >> 18) & 63u;
+      if (act[u] != 0 && post != static_cast<uint32_t>(lane))
+        atomicAdd(&acc_g[post], static_cast<float>(static_cast<int>(rc[u]) >> 24) * scale);
+    }
+  }
+}
+
+// Delivers one chunk held by a lane: 8-byte records through deliver_chunk,
+// compact ones through deliver_compact.
+template <bool RECS_LDS, bool RING_LDS, bool COMPACT, int U>
+__device__ __forceinline__ void deliver_held(const DevNet& n, const typename RecHeld<COMPACT>::type (&rc)[U],
+                                             const bool (&valid)[U], const uint32_t* ring, const uint64_t* mring,
+                                             float* acc_g, float& sum, int& isum, int lane, int t, int cur, int Dr,
+                                             int W32, uint32_t curW, uint32_t DrW) {
+  if constexpr (COMPACT) {
+    static_assert(RING_LDS && !RECS_LDS, "compact records are streamed against a ring in LDS");
+    deliver_compact<U>(rc, valid, ring, acc_g, isum, n.cscale, lane, curW, DrW);
+  } else {
+    deliver_chunk<RECS_LDS, RING_LDS, U>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+  }
+}
+
+// The lane's own-post sum of a walk segment: the float sum, or with compact
+// records the integer sum of numerators times the scale.
+template <bool COMPACT>
+__device__ __forceinline__ float take_sum(const DevNet& n, float& sum, int& isum) {
+  const float s = COMPACT ? static_cast<float>(isum) * n.cscale : sum;
+  sum = 0.f;
+  isum = 0;
+  return s;
+}
+
 // Slot mode: the chunks member, member + m, ... of the records [beg, end)
 // of one group part.  Returns the lane's own-post sum.
 template <bool RECS_LDS, bool RING_LDS, bool COMPACT = false, int U = 4>
@@ -190,6 +238,7 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
                                                const uint64_t* mring, float* acc_g, int beg, int end, int member,
                                                int m, int lane, int r0, int t, int cur, int Dr, int W32) {
   float sum = 0.f;
+  int isum = 0;
   int start = beg + member * (64 * U);
   if (start >= end) return sum;
   const uint32_t curW = static_cast<uint32_t>(cur * W32);
@@ -203,9 +252,8 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
     Held nx[U];
     bool nvalid[U];
     if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS, COMPACT, U>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
-    Rec ex[U];
-    expand_recs<COMPACT, U>(n, rc, ex);
-    deliver_chunk<RECS_LDS, RING_LDS, U>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    deliver_held<RECS_LDS, RING_LDS, COMPACT, U>(n, rc, valid, ring, mring, acc_g, sum, isum, lane, t, cur, Dr, W32,
+                                                 curW, DrW);
     if (start + stride < end) {
       if (RECS_LDS) {
         load_recs<RECS_LDS, COMPACT, U>(n, lrec, start + stride, end, lane, r0, rc, valid);
@@ -218,7 +266,7 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
       }
     }
   }
-  return sum;
+  return take_sum<COMPACT>(n, sum, isum);
 }
 
 // One part of the delivery (delay >= 2 or delay 1) as a walk over chunks.
@@ -255,6 +303,7 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
   bool valid[U];
   load_recs<RECS_LDS, COMPACT, U>(n, lrec, beg + (c - c0) * (64 * U), end, lane, r0, rc, valid);
   float sum = 0.f;
+  int isum = 0;
   for (;;) {
     // the next item
     int nlg = lg, nc = c + cstride;
@@ -284,18 +333,17 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
     bool nvalid[U];
     if (!RECS_LDS && more) load_recs<RECS_LDS, COMPACT, U>(n, lrec, nbeg + (nc - nc0) * (64 * U), nend, lane, r0, nx, nvalid);
     float* acc_g = acc + lg * kGroup;
-    Rec ex[U];
-    expand_recs<COMPACT, U>(n, rc, ex);
-    deliver_chunk<RECS_LDS, RING_LDS, U>(n, ex, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
+    deliver_held<RECS_LDS, RING_LDS, COMPACT, U>(n, rc, valid, ring, mring, acc_g, sum, isum, lane, t, cur, Dr, W32,
+                                                 curW, DrW);
     if (!more || nlg != lg) {  // flush the group's register sum (uniform)
+      const float gsum = take_sum<COMPACT>(n, sum, isum);
       if (mode == kModeSlot) {
-        ret = sum;
+        ret = gsum;
       } else if (mode == kModeOwn || (cs[lg] >= lo && cs[lg + 1] <= hi)) {
-        acc_g[lane] += sum;  // this wave is the group's only contributor in this part
+        acc_g[lane] += gsum;  // this wave is the group's only contributor in this part
       } else {
-        atomicAdd(&acc_g[lane], sum);
+        atomicAdd(&acc_g[lane], gsum);
       }
-      sum = 0.f;
     }
     if (!more) break;
     if (RECS_LDS) {

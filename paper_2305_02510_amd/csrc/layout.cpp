@@ -149,7 +149,9 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
 
 std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t max_delay, float* scale) {
   std::vector<uint32_t> out;
-  if (n > kCompactMaxNeurons || max_delay > kCompactMaxDelay || L.recs.empty()) return out;
+  const uint32_t W32 = 2u * static_cast<uint32_t>((n + kGroup - 1) / kGroup);
+  const uint32_t Dr = static_cast<uint32_t>(max_delay) + 1u;
+  if (L.recs.empty() || static_cast<uint64_t>(Dr) * W32 > kCompactMaxRing) return out;
   std::vector<float> w(L.recs.size());
   for (size_t i = 0; i < w.size(); ++i) w[i] = L.recs[i].w;
   const int32_t e = int8_exponent(w.data(), static_cast<int64_t>(w.size()));
@@ -159,7 +161,8 @@ std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t ma
   for (size_t i = 0; i < out.size(); ++i) {
     const Rec& r = L.recs[i];
     const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
-    out[i] = compact_record(k, r.meta & 0xFFFFFu, ((r.meta >> 20) & 63u) + 1u, r.meta >> 26);
+    const uint32_t pre = r.meta & 0xFFFFFu, d = ((r.meta >> 20) & 63u) + 1u;
+    out[i] = compact_record(k, (Dr - d) * W32 + (pre >> 5), pre & 31u, r.meta >> 26);
   }
   *scale = std::ldexp(1.f, -e);
   return out;

@@ -139,18 +139,18 @@ struct DevNet {
   float lscale;
 };
 
-// Compact record, 4 bytes, for nets with N <= 16384, delays <= 16 and every
-// weight k * 2^-e with |k| <= 127:
-//   bits  0..7   k (int8)      bits  8..11  delay - 1
-//   bits 12..17  post within its group      bits 18..31  pre-neuron
-constexpr int32_t kCompactMaxNeurons = 1 << 14;
-constexpr int32_t kCompactMaxDelay = 16;
-__host__ __device__ inline uint32_t compact_record(int32_t k, uint32_t pre, uint32_t delay, uint32_t post_local) {
-  return (static_cast<uint32_t>(k) & 0xFFu) | ((delay - 1u) << 8) | (post_local << 12) | (pre << 18);
-}
-__host__ __device__ inline Rec expand_compact(uint32_t c, float scale) {
-  const float w = static_cast<float>(static_cast<int8_t>(c & 0xFFu)) * scale;
-  return Rec{w, (c >> 18) | (((c >> 8) & 15u) << 20) | (((c >> 12) & 63u) << 26)};
+// Compact record, 4 bytes, for the batch kernel, whose workgroups hold the
+// spike history as a ring of D + 1 rows of 2G words in LDS; for nets with
+// (D + 1) * 2G <= 2^13 and every weight k * 2^-e with |k| <= 127:
+//   bits  0..4   the source's bit in its 32-bit word (pre mod 32)
+//   bits  5..17  offset of the source word from the current row:
+//                (D + 1 - delay) * 2G + pre / 32 (the row of step t - delay
+//                is the current row minus delay, modulo D + 1)
+//   bits 18..23  the post-neuron within its group
+//   bits 24..31  k (int8)
+constexpr uint32_t kCompactMaxRing = 1u << 13;
+__host__ __device__ inline uint32_t compact_record(int32_t k, uint32_t offset, uint32_t bit, uint32_t post_local) {
+  return (static_cast<uint32_t>(k) << 24) | (post_local << 18) | (offset << 5) | bit;
 }
 
 // Arguments of the persistent kernel: the network plus a partition of its
@@ -294,8 +294,9 @@ size_t batch_lds_bytes(const DevNet& n, int ng_max);
 int batch_blocks_per_cu(size_t lds, bool compact);
 hipError_t launch_zero_i32(int32_t* p, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int grid, size_t lds, int32_t steps, bool compact, hipStream_t s);
-// 4-byte copies of the layout's records (compact_record), or empty when the
-// net or a weight does not allow them; *scale receives 2^-e.
+// 4-byte copies of the layout's records (compact_record) for a net of n
+// neurons and maximum delay max_delay, or empty when the net or a weight
+// does not allow them; *scale receives 2^-e.
 std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t max_delay, float* scale);
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
 // Per-step kernel of nets whose D history rows do not fit in 64 KB of LDS
