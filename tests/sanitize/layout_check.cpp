@@ -12,6 +12,11 @@
 //     in a lane-owned row belongs to that lane's post; overflow records follow
 //     the rows of their section;
 //   - the delays of a section lie in its phase (part B: delay 1);
+//   - the compact records (batch kernel) decode to each record's ring
+//     offset, source bit, post and weight;
+//   - the lane-only layout holds every synapse once in its post's lane, and
+//     its lane records decode to the LDS offset and bit of the source in the
+//     phase's staged rows and to the weight;
 //   - slices of a partition are contiguous and cover all groups;
 //   - the push layout lists every synapse once under its pre-neuron.
 // Prints "ok <cases>" and exits 0, or names the first violated invariant.
@@ -110,6 +115,25 @@ static void check_layout(const Net& net, int32_t phase_rows) {
     }
   }
   for (int64_t k = 0; k < nnz; ++k) CHECK(seen[k] == 1, "synapse %lld seen %d times", (long long)k, seen[k]);
+  // compact records of the batch kernel: offset of the source word from the
+  // current ring row ((D + 1 - delay) * 2G + pre / 32), source bit, post and
+  // numerator, whenever the ring fits the offset field
+  {
+    float scale = 0.f;
+    const std::vector<uint32_t> C = compact_records(L, net.n, net.D, &scale);
+    const uint32_t W32 = 2u * static_cast<uint32_t>(G), Dr = static_cast<uint32_t>(net.D) + 1u;
+    const bool fits = static_cast<uint64_t>(Dr) * W32 <= kCompactMaxRing;
+    CHECK(C.empty() == (L.recs.empty() || !fits), "compact records: built %d, ring fits %d", (int)!C.empty(), (int)fits);
+    for (size_t i = 0; i < C.size(); ++i) {
+      const uint32_t c = C[i];
+      const Rec& r = L.recs[i];
+      const uint32_t pre = r.meta & 0xFFFFFu, d = ((r.meta >> 20) & 63u) + 1u;
+      CHECK(((c >> 5) & (kCompactMaxRing - 1u)) == (Dr - d) * W32 + (pre >> 5), "compact %zu: offset", i);
+      CHECK((c & 31u) == (pre & 31u) && ((c >> 18) & 63u) == (r.meta >> 26), "compact %zu: bit or post", i);
+      const float wk = static_cast<float>(static_cast<int8_t>(c >> 24)) * scale;
+      CHECK(wk == r.w, "compact %zu: weight", i);
+    }
+  }
   // slice partitions
   for (int32_t slices : {1, 2, 7, 256}) {
     SlicePlan p = partition_groups(L, G, slices, 128);

@@ -1,10 +1,11 @@
 """The host layout builder (csrc/layout.cpp) under AddressSanitizer and
 UndefinedBehaviorSanitizer: tests/sanitize/layout_check.cpp, built with g++
 (host code only, no GPU), builds the pull layout with and without delay
-phases, the slice partitions and the push layout of empty nets, nets with
+phases, its 4-byte compact records, the lane-only layout and its lane
+records, the slice partitions and the push layout of empty nets, nets with
 duplicates, self-loops and signed-zero weights, hub nets whose posts
 overflow the lane-owned rows, delays up to 64 and 2^20 neurons, and checks
-the invariants the kernels rely on."""
+the invariants the kernels rely on (every record field decoded back)."""
 import os
 import shutil
 import subprocess
