@@ -877,7 +877,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
                 static_cast<long long>(nnz));
   HostPush H = build_push_layout(n->d.N, n->d.Npad, nnz, pre, post, w, delay);
   float cscale = 0.f;
-  const std::vector<uint32_t> C = compact_records(L, n->d.N, n->d.D, &cscale);
+  std::vector<uint32_t> C = compact_records(L, n->d.N, n->d.D, &cscale);
+  if (!C.empty()) C.resize(C.size() + static_cast<size_t>(kCompactChunkRows) * kGroup, 0u);  // slack of one chunk
   // wide nets with every delay staged: a lane-only copy of the layout as
   // 4-byte lane records, kept when it is at most 80% of the 8-byte records'
   // bytes

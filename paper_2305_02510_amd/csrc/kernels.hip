@@ -71,7 +71,7 @@ __host__ __device__ __forceinline__ int acc_rows(int ng_max, int nwave) {
 }
 
 // Records [k, k + 4 * 64) of the calling lane's chunk (four, 64 apart);
-// valid[u] is false past `end`.  Loads are issued unconditionally with the
+// valid(u) is false past `end`.  Loads are issued unconditionally with the
 // index clamped into the chunk (start < end), so the four are in flight
 // together; deliver_chunk masks the invalid ones.  COMPACT reads the 4-byte
 // copies of the records (n.crecs, see compact_record).
@@ -86,20 +86,44 @@ struct RecHeld<true> {
   using type = uint32_t;
 };
 
+// Which records of a held chunk are inside their section: a flag per
+// record, or with COMPACT (sections of whole rows) the count of valid rows.
+template <bool COMPACT, int U>
+struct ChunkValid {
+  bool v[U];
+  __device__ __forceinline__ bool operator()(int u) const { return v[u]; }
+};
+template <int U>
+struct ChunkValid<true, U> {
+  int rows;
+  __device__ __forceinline__ bool operator()(int u) const { return u < rows; }
+};
+
 template <bool RECS_LDS, bool COMPACT = false, int U = 4>
 __device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int start, int end, int lane, int r0,
-                                          typename RecHeld<COMPACT>::type (&rc)[U], bool (&valid)[U]) {
+                                          typename RecHeld<COMPACT>::type (&rc)[U], ChunkValid<COMPACT, U>& valid) {
+  if constexpr (COMPACT) {
+    // start and end are row boundaries: a row is valid or masked as a whole,
+    // and a masked row's loads stay inside the array's slack (one chunk),
+    // so the loads need no clamp and take their row from an immediate offset
+    // (through the global address space: the pointer comes from device
+    // memory, and a flat load would also hold back the waits for LDS reads)
+    const __attribute__((address_space(1))) uint32_t* src =
+        (const __attribute__((address_space(1))) uint32_t*)(n.crecs + start + lane);
+    valid.rows = (end - start) >> 6;
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int k = start + lane + 64 * u;
-    valid[u] = k < end;
-    const int kc = k < end ? k : end - 1;
-    if constexpr (COMPACT) {
-      rc[u] = n.crecs[kc];
-    } else if constexpr (RECS_LDS) {
-      rc[u] = lrec[kc - r0];
-    } else {
-      rc[u] = n.recs[kc];
+    for (int u = 0; u < U; ++u) rc[u] = src[64 * u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = start + lane + 64 * u;
+      valid.v[u] = k < end;
+      const int kc = k < end ? k : end - 1;
+      if constexpr (RECS_LDS) {
+        rc[u] = lrec[kc - r0];
+      } else {
+        rc[u] = n.recs[kc];
+      }
     }
   }
 }
@@ -119,7 +143,7 @@ constexpr int kModeSlot = 0, kModeOwn = 1, kModeRange = 2;
 // The U records of one chunk held by a lane: source bits from the ring
 // (or the mailbox), own-post weights into *sum, other posts atomically.
 template <bool RECS_LDS, bool RING_LDS, int U = 4>
-__device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U], const bool (&valid)[U],
+__device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U], const ChunkValid<false, U>& valid,
                                               const uint32_t* ring, const uint64_t* mring, float* acc_g, float& sum,
                                               int lane, int t, int cur, int Dr, int W32, uint32_t curW, uint32_t DrW) {
   uint32_t bit[U];
@@ -135,7 +159,7 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U
       // ring, so no test of t - d is needed.
       uint32_t adr = curW + (mt & 0xFFFFu);
       adr = min(adr, adr - DrW);
-      bit[u] = (ring[adr] >> ((mt >> 16) & 31u)) & static_cast<uint32_t>(valid[u]);
+      bit[u] = (ring[adr] >> ((mt >> 16) & 31u)) & static_cast<uint32_t>(valid(u));
       continue;
     }
     const int d = static_cast<int>((mt >> 20) & 63u) + 1;
@@ -143,10 +167,10 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U
     int slot = cur - d;
     if (slot < 0) slot += Dr;
     if (RING_LDS) {
-      bit[u] = (ring[slot * W32 + (pre >> 5)] >> (pre & 31u)) & static_cast<uint32_t>(valid[u]);
+      bit[u] = (ring[slot * W32 + (pre >> 5)] >> (pre & 31u)) & static_cast<uint32_t>(valid(u));
     } else {
       bit[u] = 0u;
-      if (valid[u] && t - d >= 0) {
+      if (valid(u) && t - d >= 0) {
         const uint32_t word =
             static_cast<uint32_t>(load_dev(mring + static_cast<size_t>(slot) * n.B * W32 + (pre >> 5)));
         bit[u] = (word >> (pre & 31u)) & 1u;
@@ -177,7 +201,7 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U
 // scaled once when the sum is flushed), other posts' weights are added
 // atomically.
 template <int U>
-__device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const bool (&valid)[U], const uint32_t* ring,
+__device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const ChunkValid<true, U>& valid, const uint32_t* ring,
                                                 float* acc_g, int& isum, float scale, int lane, uint32_t curW,
                                                 uint32_t DrW) {
   int act[U];
@@ -187,7 +211,7 @@ __device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const b
     uint32_t adr = curW + ((c >> 5) & (kCompactMaxRing - 1u));
     adr = min(adr, adr - DrW);  // the row of step t - d: cur - d modulo Dr
     // (v_bfe reads only the offset's low 5 bits: the source's bit)
-    act[u] = __builtin_amdgcn_sbfe(static_cast<int>(ring[adr]), c, 1u) & -static_cast<int>(valid[u]);
+    act[u] = valid(u) ? __builtin_amdgcn_sbfe(static_cast<int>(ring[adr]), c, 1u) : 0;
   }
   bool other = false;  // an active overflow record of another lane's post (rare)
 #pragma unroll
@@ -210,7 +234,7 @@ __device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const b
 // compact ones through deliver_compact.
 template <bool RECS_LDS, bool RING_LDS, bool COMPACT, int U>
 __device__ __forceinline__ void deliver_held(const DevNet& n, const typename RecHeld<COMPACT>::type (&rc)[U],
-                                             const bool (&valid)[U], const uint32_t* ring, const uint64_t* mring,
+                                             const ChunkValid<COMPACT, U>& valid, const uint32_t* ring, const uint64_t* mring,
                                              float* acc_g, float& sum, int& isum, int lane, int t, int cur, int Dr,
                                              int W32, uint32_t curW, uint32_t DrW) {
   if constexpr (COMPACT) {
@@ -246,11 +270,11 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
   const int stride = m * (64 * U);
   using Held = typename RecHeld<COMPACT>::type;
   Held rc[U];
-  bool valid[U];
+  ChunkValid<COMPACT, U> valid;
   load_recs<RECS_LDS, COMPACT, U>(n, lrec, start, end, lane, r0, rc, valid);
   for (; start < end; start += stride) {
     Held nx[U];
-    bool nvalid[U];
+    ChunkValid<COMPACT, U> nvalid;
     if (!RECS_LDS && start + stride < end) load_recs<RECS_LDS, COMPACT, U>(n, lrec, start + stride, end, lane, r0, nx, nvalid);
     deliver_held<RECS_LDS, RING_LDS, COMPACT, U>(n, rc, valid, ring, mring, acc_g, sum, isum, lane, t, cur, Dr, W32,
                                                  curW, DrW);
@@ -259,10 +283,8 @@ __device__ __forceinline__ float deliver_group(const DevNet& n, const Rec* lrec,
         load_recs<RECS_LDS, COMPACT, U>(n, lrec, start + stride, end, lane, r0, rc, valid);
       } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          rc[u] = nx[u];
-          valid[u] = nvalid[u];
-        }
+        for (int u = 0; u < U; ++u) rc[u] = nx[u];
+        valid = nvalid;
       }
     }
   }
@@ -300,7 +322,7 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
   int beg = bp[lg], end = ep[lg], c0 = cs[lg], cend = item_end(lg);
   using Held = typename RecHeld<COMPACT>::type;
   Held rc[U];
-  bool valid[U];
+  ChunkValid<COMPACT, U> valid;
   load_recs<RECS_LDS, COMPACT, U>(n, lrec, beg + (c - c0) * (64 * U), end, lane, r0, rc, valid);
   float sum = 0.f;
   int isum = 0;
@@ -330,7 +352,7 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
       ncend = item_end(nlg);
     }
     Held nx[U];
-    bool nvalid[U];
+    ChunkValid<COMPACT, U> nvalid;
     if (!RECS_LDS && more) load_recs<RECS_LDS, COMPACT, U>(n, lrec, nbeg + (nc - nc0) * (64 * U), nend, lane, r0, nx, nvalid);
     float* acc_g = acc + lg * kGroup;
     deliver_held<RECS_LDS, RING_LDS, COMPACT, U>(n, rc, valid, ring, mring, acc_g, sum, isum, lane, t, cur, Dr, W32,
@@ -350,10 +372,8 @@ __device__ __forceinline__ float deliver(const DevNet& n, const Rec* lrec, const
       load_recs<RECS_LDS, COMPACT, U>(n, lrec, nbeg + (nc - nc0) * (64 * U), nend, lane, r0, rc, valid);
     } else {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        rc[u] = nx[u];
-        valid[u] = nvalid[u];
-      }
+      for (int u = 0; u < U; ++u) rc[u] = nx[u];
+      valid = nvalid;
     }
     lg = nlg;
     c = nc;
@@ -661,7 +681,7 @@ hipError_t launch_prefill_mailbox(const SimArgs& a, int32_t t0, hipStream_t s) {
 // 512-net batch: 8 -> 115 ms, 12 -> 109 ms, 16 -> 119 ms per 500-step run),
 // else 4.
 template <bool COMPACT>
-constexpr int kBatchU = COMPACT ? 12 : 4;
+constexpr int kBatchU = COMPACT ? kCompactChunkRows : 4;
 
 // COMPACT: every network of the batch has 4-byte record copies (n.crecs).
 template <bool COMPACT>

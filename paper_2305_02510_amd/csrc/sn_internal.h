@@ -149,6 +149,12 @@ struct DevNet {
 //   bits 18..23  the post-neuron within its group
 //   bits 24..31  k (int8)
 constexpr uint32_t kCompactMaxRing = 1u << 13;
+// Records per lane in one chunk of the batch kernel with compact records.
+// Sections are whole rows of 64, so the kernel masks a chunk's rows past its
+// section's end as a whole and loads them unclamped: the device array
+// carries one chunk (kCompactChunkRows rows) of zero records as slack after
+// its last record.
+constexpr int32_t kCompactChunkRows = 12;
 __host__ __device__ inline uint32_t compact_record(int32_t k, uint32_t offset, uint32_t bit, uint32_t post_local) {
   return (static_cast<uint32_t>(k) << 24) | (post_local << 18) | (offset << 5) | bit;
 }
