@@ -196,36 +196,49 @@ __device__ __forceinline__ void deliver_chunk(const DevNet& n, const Rec (&rc)[U
 // The U compact records of one chunk held by a lane (batch kernel: ring in
 // LDS, records streamed from memory).  A record carries its source word's
 // offset from the current ring row, so the lookup is one add and a wrap,
-// and its source bit, extracted sign-extended into an all-ones mask.  The
-// numerators k of active own-post records are summed as an integer (exact;
-// scaled once when the sum is flushed), other posts' weights are added
-// atomically.
+// and its source bit, extracted sign-extended into an all-ones mask.  Every
+// active record's numerator k is added to the lane's integer sum (exact;
+// scaled once when the sum is flushed); a record of another lane's post (an
+// overflow record: nonzero post field) is rare, so it is taken back out of
+// the sum afterwards and its weight added to its post atomically.
+// The ring of the batch kernel holds every row twice (rows r and r + Dr), so
+// the row of step t - d, cur + Dr - d, needs no wrap.
 template <int U>
-__device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const ChunkValid<true, U>& valid, const uint32_t* ring,
-                                                float* acc_g, int& isum, float scale, int lane, uint32_t curW,
-                                                uint32_t DrW) {
+__device__ __forceinline__ void deliver_compact(const uint32_t (&rc)[U], const ChunkValid<true, U>& valid,
+                                                const uint32_t* ring, float* acc_g, int& isum, float scale, int lane,
+                                                uint32_t curW) {
+  constexpr uint32_t kPostField = 63u << 18;
   int act[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
+  uint32_t other = 0;  // nonzero: an active overflow record in the chunk
+  // rows past the section's end hold records of the next section (or the
+  // slack), whose ring offsets are in range: every read is issued, and the
+  // masked rows' bits are cleared arithmetically (a chunk is full unless it
+  // is its section's last)
+  auto deliver = [&](int u, int mask) {
     const uint32_t c = rc[u];
-    uint32_t adr = curW + ((c >> 5) & (kCompactMaxRing - 1u));
-    adr = min(adr, adr - DrW);  // the row of step t - d: cur - d modulo Dr
+    const uint32_t adr = curW + ((c >> 5) & (kCompactMaxRing - 1u));
     // (v_bfe reads only the offset's low 5 bits: the source's bit)
-    act[u] = valid(u) ? __builtin_amdgcn_sbfe(static_cast<int>(ring[adr]), c, 1u) : 0;
-  }
-  bool other = false;  // an active overflow record of another lane's post (rare)
+    act[u] = __builtin_amdgcn_sbfe(static_cast<int>(ring[adr]), c, 1u) & mask;
+    isum += act[u] & (static_cast<int>(c) >> 24);
+    other |= static_cast<uint32_t>(act[u]) & c & kPostField;
+  };
+  const int rows = __builtin_amdgcn_readfirstlane(valid.rows);  // uniform
+  if (rows >= U) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const bool own = ((rc[u] >> 18) & 63u) == static_cast<uint32_t>(lane);
-    isum += (own ? act[u] : 0) & (static_cast<int>(rc[u]) >> 24);
-    other |= act[u] != 0 && !own;
+    for (int u = 0; u < U; ++u) deliver(u, -1);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) deliver(u, u < rows ? -1 : 0);
   }
   if (other) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t post = (rc[u] >> 18) & 63u;
-      if (act[u] != 0 && post != static_cast<uint32_t>(lane))
-        atomicAdd(&acc_g[post], static_cast<float>(static_cast<int>(rc[u]) >> 24) * scale);
+      const uint32_t c = rc[u];
+      if (act[u] != 0 && (c & kPostField) != 0) {
+        const int k = static_cast<int>(c) >> 24;
+        isum -= k;
+        atomicAdd(&acc_g[(lane + (c >> 18)) & 63], static_cast<float>(k) * scale);
+      }
     }
   }
 }
@@ -239,7 +252,7 @@ __device__ __forceinline__ void deliver_held(const DevNet& n, const typename Rec
                                              int W32, uint32_t curW, uint32_t DrW) {
   if constexpr (COMPACT) {
     static_assert(RING_LDS && !RECS_LDS, "compact records are streamed against a ring in LDS");
-    deliver_compact<U>(rc, valid, ring, acc_g, isum, n.cscale, lane, curW, DrW);
+    deliver_compact<U>(rc, valid, ring, acc_g, isum, n.cscale, lane, curW);
   } else {
     deliver_chunk<RECS_LDS, RING_LDS, U>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
   }
@@ -417,7 +430,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
   uint64_t* mring = a.mailbox + static_cast<size_t>(b) * W32;
 
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);
-  float* acc = reinterpret_cast<float*>(ring + (RING_LDS ? Dr * W32 : 0));  // [nacc][ng_max][64]
+  // with COMPACT the ring holds every row twice (see deliver_compact)
+  constexpr int kRingCopies = COMPACT ? 2 : 1;
+  const int ring_second = COMPACT ? Dr * W32 : 0;  // offset of the second copy
+  float* acc = reinterpret_cast<float*>(ring + (RING_LDS ? kRingCopies * Dr * W32 : 0));  // [nacc][ng_max][64]
   float* part = acc + acc_rows(a.ng_max, nwave) * kGroup;                    // [kMaxWaves][64]
   int* gsp = reinterpret_cast<int*>(part + kMaxWaves * kGroup);  // [ng + 1] starts, [ng] splits
   int* csA = gsp + 2 * a.ng_max + 1;                              // [ng + 1] chunk offsets, delay >= 2
@@ -428,7 +444,7 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
   if (tid == 0) abort_flag = 0;
   __syncthreads();
   if (RING_LDS) {
-    for (int i = tid; i < Dr * W32; i += nthr) ring[i] = 0u;
+    for (int i = tid; i < kRingCopies * Dr * W32; i += nthr) ring[i] = 0u;
   }
   for (int i = tid; i < acc_rows(a.ng_max, nwave) * kGroup; i += nthr) acc[i] = 0.f;
   for (int i = tid; i <= ng; i += nthr) gsp[i] = n.gptr[g0 + i];
@@ -464,6 +480,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
         const uint64_t wv = hist[static_cast<size_t>(ts) * rstride + i];
         ring[slot * W32 + 2 * i] = static_cast<uint32_t>(wv);
         ring[slot * W32 + 2 * i + 1] = static_cast<uint32_t>(wv >> 32);
+        if (COMPACT) {
+          ring[ring_second + slot * W32 + 2 * i] = static_cast<uint32_t>(wv);
+          ring[ring_second + slot * W32 + 2 * i + 1] = static_cast<uint32_t>(wv >> 32);
+        }
       }
     }
   }
@@ -568,6 +588,7 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
           v = load_dev(p);
         }
         if (RING_LDS) ring[prev * W32 + i] = static_cast<uint32_t>(v);
+        if (RING_LDS && COMPACT) ring[ring_second + prev * W32 + i] = static_cast<uint32_t>(v);
       }
     }
     __syncthreads();
@@ -605,7 +626,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
         const uint64_t sw = __ballot(s);
         const int g = g0 + lg;
         if (lane == 0) n.raster[row_word(n, t, b, g)] = sw;
-        if (RING_LDS && lane < 2) ring[cur * W32 + 2 * g + lane] = static_cast<uint32_t>(sw >> (32 * lane));
+        if (RING_LDS && lane < 2) {
+          ring[cur * W32 + 2 * g + lane] = static_cast<uint32_t>(sw >> (32 * lane));
+          if (COMPACT) ring[ring_second + cur * W32 + 2 * g + lane] = static_cast<uint32_t>(sw >> (32 * lane));
+        }
         if (use_mail && lane < 2) {
           const uint64_t tagged = (static_cast<uint64_t>(t + 1) << 32) | ((sw >> (32 * lane)) & 0xFFFFFFFFull);
           store_dev(mring + static_cast<size_t>(cur) * n.B * W32 + 2 * g + lane, tagged);
@@ -724,9 +748,12 @@ size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, b
   return bytes + 64;  // static LDS of the kernel
 }
 
+// (a net with compact records may run in a batch that keeps two copies of
+// its ring)
 size_t batch_lds_bytes(const DevNet& n, int ng_max) {
   return sim_lds_bytes(n, ng_max, 0, kBatchThreads / 64, false, true) - 64 +
-         static_cast<size_t>(5) * ng_max * kGroup * sizeof(float);
+         static_cast<size_t>(5) * ng_max * kGroup * sizeof(float) +
+         (n.crecs ? static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t) : 0);
 }
 
 int batch_blocks_per_cu(size_t lds, bool compact) {

@@ -162,7 +162,8 @@ std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t ma
     const Rec& r = L.recs[i];
     const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
     const uint32_t pre = r.meta & 0xFFFFFu, d = ((r.meta >> 20) & 63u) + 1u;
-    out[i] = compact_record(k, (Dr - d) * W32 + (pre >> 5), pre & 31u, r.meta >> 26);
+    const uint32_t delta = ((r.meta >> 26) - static_cast<uint32_t>(i % kGroup)) & 63u;  // 0: the lane's own post
+    out[i] = compact_record(k, (Dr - d) * W32 + (pre >> 5), pre & 31u, delta);
   }
   *scale = std::ldexp(1.f, -e);
   return out;

@@ -146,7 +146,9 @@ struct DevNet {
 //   bits  5..17  offset of the source word from the current row:
 //                (D + 1 - delay) * 2G + pre / 32 (the row of step t - delay
 //                is the current row minus delay, modulo D + 1)
-//   bits 18..23  the post-neuron within its group
+//   bits 18..23  (post-neuron within its group - lane) mod 64, where the lane
+//                is the record's position mod 64: 0 for the lane-owned rows,
+//                so only overflow records carry a nonzero value
 //   bits 24..31  k (int8)
 constexpr uint32_t kCompactMaxRing = 1u << 13;
 // Records per lane in one chunk of the batch kernel with compact records.
@@ -155,8 +157,8 @@ constexpr uint32_t kCompactMaxRing = 1u << 13;
 // carries one chunk (kCompactChunkRows rows) of zero records as slack after
 // its last record.
 constexpr int32_t kCompactChunkRows = 12;
-__host__ __device__ inline uint32_t compact_record(int32_t k, uint32_t offset, uint32_t bit, uint32_t post_local) {
-  return (static_cast<uint32_t>(k) << 24) | (post_local << 18) | (offset << 5) | bit;
+__host__ __device__ inline uint32_t compact_record(int32_t k, uint32_t offset, uint32_t bit, uint32_t post_delta) {
+  return (static_cast<uint32_t>(k) << 24) | (post_delta << 18) | (offset << 5) | bit;
 }
 
 // Arguments of the persistent kernel: the network plus a partition of its

@@ -116,8 +116,9 @@ static void check_layout(const Net& net, int32_t phase_rows) {
   }
   for (int64_t k = 0; k < nnz; ++k) CHECK(seen[k] == 1, "synapse %lld seen %d times", (long long)k, seen[k]);
   // compact records of the batch kernel: offset of the source word from the
-  // current ring row ((D + 1 - delay) * 2G + pre / 32), source bit, post and
-  // numerator, whenever the ring fits the offset field
+  // current ring row ((D + 1 - delay) * 2G + pre / 32), source bit, post
+  // (relative to the record's lane) and numerator, whenever the ring fits the
+  // offset field
   {
     float scale = 0.f;
     const std::vector<uint32_t> C = compact_records(L, net.n, net.D, &scale);
@@ -129,7 +130,7 @@ static void check_layout(const Net& net, int32_t phase_rows) {
       const Rec& r = L.recs[i];
       const uint32_t pre = r.meta & 0xFFFFFu, d = ((r.meta >> 20) & 63u) + 1u;
       CHECK(((c >> 5) & (kCompactMaxRing - 1u)) == (Dr - d) * W32 + (pre >> 5), "compact %zu: offset", i);
-      CHECK((c & 31u) == (pre & 31u) && ((c >> 18) & 63u) == (r.meta >> 26), "compact %zu: bit or post", i);
+      CHECK((c & 31u) == (pre & 31u) && ((((c >> 18) + i) & 63u) == (r.meta >> 26)), "compact %zu: bit or post", i);
       const float wk = static_cast<float>(static_cast<int8_t>(c >> 24)) * scale;
       CHECK(wk == r.w, "compact %zu: weight", i);
     }
