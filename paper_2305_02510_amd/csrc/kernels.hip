@@ -106,13 +106,19 @@ __device__ __forceinline__ void load_recs(const DevNet& n, const Rec* lrec, int 
     // start and end are row boundaries: a row is valid or masked as a whole,
     // and a masked row's loads stay inside the array's slack (one chunk),
     // so the loads need no clamp and take their row from an immediate offset
-    // (through the global address space: the pointer comes from device
-    // memory, and a flat load would also hold back the waits for LDS reads)
-    const __attribute__((address_space(1))) uint32_t* src =
-        (const __attribute__((address_space(1))) uint32_t*)(n.crecs + start + lane);
     valid.rows = (end - start) >> 6;
+    if constexpr (RECS_LDS) {  // the slice's records staged in LDS (4 bytes each)
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(lrec) + (start - r0) + lane;
 #pragma unroll
-    for (int u = 0; u < U; ++u) rc[u] = src[64 * u];
+      for (int u = 0; u < U; ++u) rc[u] = src[64 * u];
+    } else {
+      // (through the global address space: the pointer comes from device
+      // memory, and a flat load would also hold back the waits for LDS reads)
+      const __attribute__((address_space(1))) uint32_t* src =
+          (const __attribute__((address_space(1))) uint32_t*)(n.crecs + start + lane);
+#pragma unroll
+      for (int u = 0; u < U; ++u) rc[u] = src[64 * u];
+    }
   } else {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -251,7 +257,7 @@ __device__ __forceinline__ void deliver_held(const DevNet& n, const typename Rec
                                              float* acc_g, float& sum, int& isum, int lane, int t, int cur, int Dr,
                                              int W32, uint32_t curW, uint32_t DrW) {
   if constexpr (COMPACT) {
-    static_assert(RING_LDS && !RECS_LDS, "compact records are streamed against a ring in LDS");
+    static_assert(RING_LDS, "compact records address a ring in LDS");
     deliver_compact<U>(rc, valid, ring, acc_g, isum, n.cscale, lane, curW);
   } else {
     deliver_chunk<RECS_LDS, RING_LDS, U>(n, rc, valid, ring, mring, acc_g, sum, lane, t, cur, Dr, W32, curW, DrW);
@@ -461,7 +467,10 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
     csA[ng] = ca;
     csB[ng] = cb;
   }
-  if (RECS_LDS) {
+  if (RECS_LDS && COMPACT) {  // 4-byte records as they are, then one chunk of zero slack
+    uint32_t* l32 = reinterpret_cast<uint32_t*>(lrec);
+    for (int i = tid; i < nrec + 64 * U; i += nthr) l32[i] = i < nrec ? n.crecs[r0 + i] : 0u;
+  } else if (RECS_LDS) {
     for (int i = tid; i < nrec; i += nthr) {
       Rec r = n.recs[r0 + i];
       if (RING_LDS) r.meta = lds_meta(r.meta, Dr, W32);
@@ -655,13 +664,15 @@ __device__ __forceinline__ bool sim_body(const SimArgs& a, int w, int b, int t0,
   return true;
 }
 
-template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI>
+// COMPACT: the slice's compact records (n.crecs) staged in LDS, 4 bytes each,
+// against a doubled ring (records and ring both in LDS).
+template <int NPT, bool RECS_LDS, bool RING_LDS, bool MULTI, bool COMPACT = false>
 __global__ __launch_bounds__(1024) void k_sim(const SimArgs a, int t0, int steps) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int abort_flag;
   const int w = MULTI ? static_cast<int>(blockIdx.x) : 0;
   const int b = MULTI ? static_cast<int>(blockIdx.y) : static_cast<int>(blockIdx.x);
-  sim_body<NPT, RECS_LDS, RING_LDS, MULTI>(a, w, b, t0, steps, smem, abort_flag);
+  sim_body<NPT, RECS_LDS, RING_LDS, MULTI, false, COMPACT>(a, w, b, t0, steps, smem, abort_flag);
 }
 
 // Mailbox before a launch starting at t0: slot of row r (t0 - D <= r < t0,
@@ -739,12 +750,15 @@ constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kMaxNpt = 8;
 
 // LDS of sim_body: [ring][accumulators][partial sums][group offsets][records]
-size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, bool recs_lds, bool ring_lds) {
+// (compact: 4-byte records plus one 4-row chunk of slack, two ring copies)
+size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, bool recs_lds, bool ring_lds,
+                     bool compact) {
   size_t bytes = static_cast<size_t>(acc_rows(ng_max, nwave)) * kGroup * sizeof(float);
   bytes += static_cast<size_t>(kMaxWaves) * kGroup * sizeof(float);
   bytes += static_cast<size_t>(4 * ng_max + 4) * sizeof(int);
-  if (ring_lds) bytes += static_cast<size_t>(n.D + 1) * 2 * n.G * sizeof(uint32_t);
-  if (recs_lds) bytes += static_cast<size_t>(max_recs) * sizeof(Rec);
+  if (ring_lds) bytes += static_cast<size_t>(compact ? 2 : 1) * (n.D + 1) * 2 * n.G * sizeof(uint32_t);
+  if (recs_lds)
+    bytes += compact ? static_cast<size_t>(max_recs + 4 * 64) * sizeof(uint32_t) : static_cast<size_t>(max_recs) * sizeof(Rec);
   return bytes + 64;  // static LDS of the kernel
 }
 
@@ -795,9 +809,9 @@ int sim_npt(int ng_max, int64_t max_recs) {
   return (ng_max + nw - 1) / nw;
 }
 
-template <int NPT, bool RL, bool GL, bool MULTI>
+template <int NPT, bool RL, bool GL, bool MULTI, bool COMPACT = false>
 static hipError_t launch_sim_t(const SimArgs& a, int32_t t0, int32_t steps, hipStream_t s, size_t lds) {
-  const void* fn = reinterpret_cast<const void*>(&k_sim<NPT, RL, GL, MULTI>);
+  const void* fn = reinterpret_cast<const void*>(&k_sim<NPT, RL, GL, MULTI, COMPACT>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      static_cast<int>(kLdsLimit - 64));
   if (e != hipSuccess) return e;
@@ -807,15 +821,23 @@ static hipError_t launch_sim_t(const SimArgs& a, int32_t t0, int32_t steps, hipS
     void* args[] = {const_cast<SimArgs*>(&a), &t0, &steps};
     return hipLaunchCooperativeKernel(fn, grid, block, args, static_cast<unsigned>(lds), s);
   }
-  hipLaunchKernelGGL((k_sim<NPT, RL, GL, MULTI>), dim3(a.n.B), block, lds, s, a, t0, steps);
+  hipLaunchKernelGGL((k_sim<NPT, RL, GL, MULTI, COMPACT>), dim3(a.n.B), block, lds, s, a, t0, steps);
   return hipGetLastError();
 }
 
 template <bool MULTI>
-static hipError_t launch_sim_m(const SimArgs& a, bool rl, bool gl, int32_t t0, int32_t steps, hipStream_t s,
-                               size_t lds) {
+static hipError_t launch_sim_m(const SimArgs& a, bool rl, bool gl, bool compact, int32_t t0, int32_t steps,
+                               hipStream_t s, size_t lds) {
   const int npt = sim_npt(a.ng_max, a.max_recs);
   const int np2 = npt <= 1 ? 1 : npt <= 2 ? 2 : npt <= 4 ? 4 : 8;
+  if (compact) {  // records and ring in LDS
+    switch (np2) {
+      case 1: return launch_sim_t<1, true, true, MULTI, true>(a, t0, steps, s, lds);
+      case 2: return launch_sim_t<2, true, true, MULTI, true>(a, t0, steps, s, lds);
+      case 4: return launch_sim_t<4, true, true, MULTI, true>(a, t0, steps, s, lds);
+      default: return launch_sim_t<8, true, true, MULTI, true>(a, t0, steps, s, lds);
+    }
+  }
   const int key = np2 * 4 + (rl ? 2 : 0) + (gl ? 1 : 0);
   switch (key) {
 #define SN_CASE(NP)                                                                  \
@@ -835,14 +857,24 @@ static hipError_t launch_sim_m(const SimArgs& a, bool rl, bool gl, int32_t t0, i
 hipError_t launch_sim(const SimArgs& a, bool recs_lds, bool ring_lds, int32_t t0, int32_t steps, hipStream_t s) {
   if (sim_npt(a.ng_max, a.max_recs) > kMaxNpt) return hipErrorInvalidValue;
   const int nwave = sim_threads(a.ng_max, a.max_recs) / kGroup;
-  const size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, nwave, recs_lds, ring_lds) - 64;
+  size_t lds = sim_lds_bytes(a.n, a.ng_max, a.max_recs, nwave, recs_lds, ring_lds) - 64;
   if (lds + 64 > kLdsLimit) return hipErrorInvalidValue;
+  // records and ring in LDS: the compact records when the net has them and
+  // they fit (half the record bytes, a doubled ring)
+  bool compact = false;
+  if (recs_lds && ring_lds && a.n.crecs) {
+    const size_t lc = sim_lds_bytes(a.n, a.ng_max, a.max_recs, nwave, true, true, true) - 64;
+    if (lc + 64 <= kLdsLimit) {
+      compact = true;
+      lds = lc;
+    }
+  }
   if (a.P > 1 || !ring_lds) {
     const hipError_t e = launch_prefill_mailbox(a, t0, s);
     if (e != hipSuccess) return e;
   }
-  if (a.P > 1) return launch_sim_m<true>(a, recs_lds, ring_lds, t0, steps, s, lds);
-  return launch_sim_m<false>(a, recs_lds, ring_lds, t0, steps, s, lds);
+  if (a.P > 1) return launch_sim_m<true>(a, recs_lds, ring_lds, compact, t0, steps, s, lds);
+  return launch_sim_m<false>(a, recs_lds, ring_lds, compact, t0, steps, s, lds);
 }
 
 

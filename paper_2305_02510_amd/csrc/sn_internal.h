@@ -292,7 +292,8 @@ hipError_t bptt_backward(const sn_bptt_desc& d, const float* W, const float* x, 
                          float* dW, hipStream_t s);
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
-size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, bool recs_lds, bool ring_lds);
+size_t sim_lds_bytes(const DevNet& n, int ng_max, int64_t max_recs, int nwave, bool recs_lds, bool ring_lds,
+                     bool compact = false);
 size_t lds_limit();
 int sim_threads(int ng_max, int64_t max_recs);
 int sim_npt(int ng_max, int64_t max_recs);
