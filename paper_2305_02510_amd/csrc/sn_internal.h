@@ -74,7 +74,8 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
 // phase_rows > 0 splits part A into delay phases of that many delays each
 // (see HostLayout), for nets of at least two phases; 0 = no phases.
 // lane_only: no overflow sections, every record in its post's lane (as many
-// rows as a part's largest in-degree).
+// rows as a section's largest in-degree), the delay-1 records in phase 0's
+// section (part B empty).
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
                         const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0, bool lane_only = false);
 
