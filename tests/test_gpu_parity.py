@@ -218,6 +218,30 @@ def test_wide_step_lane_records(gpu, oracle, n, p, D, trials):
     assert 0.002 < s.mean() < 0.6, s.mean()
 
 
+@pytest.mark.parametrize("kind", ["compact", "ring_too_wide", "wide_numerators"])
+def test_persist_record_formats(gpu, oracle, kind):
+    """The persistent path with each record format it stages in LDS:
+    compact 4-byte records against a doubled ring (int8 numerators, a ring
+    of (D + 1) * 2G <= 2^13 words), and 8-byte records when the ring is too
+    large for the compact offset (N = 20,000) or a weight needs a numerator
+    beyond int8 (w = 129/64: no power of two makes every weight an int8
+    numerator)."""
+    if kind == "compact":
+        net = wl.large_sparse(71, n=3000, p=0.02, steps=150)
+    elif kind == "ring_too_wide":
+        net = wl.large_sparse(72, n=20_000, p=0.002, steps=120)
+    else:
+        net = wl.large_sparse(73, n=3000, p=0.02, steps=150)
+        w = net.weight.copy()
+        w[::997] = 129 / 64
+        net = dataclasses.replace(net, weight=w, name=net.name + "_wide_numerators")
+    res = oracle.run_sparse(net)
+    s, V, r, used = simulate(gpu, net, "persist", chunks=[1, 50, net.steps - 51])
+    assert used == "persist"
+    assert_parity(net, res, s, V, r, f"persist {kind}")
+    assert 0.01 < s.mean() < 0.6, s.mean()
+
+
 def test_large_sparse_low_rate(gpu, oracle):
     net = wl.large_sparse_low(2, steps=300)
     res = oracle.run_sparse(net)
