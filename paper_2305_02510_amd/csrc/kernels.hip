@@ -897,6 +897,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
   __shared__ float acc[kGroup];
   __shared__ float part[WAVES][kGroup];
   __shared__ uint64_t hq_s[STDP ? kGroup : 1];  // H_{t-1} of this group's neurons
+  __shared__ float tab_s[STDP ? 32 : 1];         // the rule's tables: ltp [0, 16), ltd [16, 32)
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* ring = reinterpret_cast<uint32_t*>(smem);  // [D][2G]: row t - d at (d - 1)
   const int g = blockIdx.x;
@@ -923,6 +924,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
     R = n.refr[j];
     ew = n.ext[row_word(n, t, b, g)];
     if (STDP) hq_s[lane] = sa.hist[static_cast<size_t>((t - 1) & 1) * n.Npad + j];
+    // the tables in LDS: an amplitude is then an LDS read, not a load from
+    // the kernel arguments in memory with a per-lane index
+    if (STDP && lane < 32) tab_s[lane] = lane < 16 ? sa.ltp[lane] : sa.ltd[lane - 16];
   }
   const int beg = n.gptr[g];
   const int end = n.gptr[g + 1];
@@ -970,11 +974,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
         if (d + sa.window <= 64) {
           if (hq & 1ull) {
             const uint32_t x = static_cast<uint32_t>(hp[u] >> d) & wmask;
-            if (x) change += sa.ltp[__builtin_ctz(x)];
+            if (x) change += tab_s[__builtin_ctz(x)];
           }
           if ((hp[u] >> d) & 1ull) {
             const uint32_t x = static_cast<uint32_t>(hq >> 1) & wmask;
-            if (x) change -= sa.ltd[__builtin_ctz(x)];
+            if (x) change -= tab_s[16 + __builtin_ctz(x)];
           }
         } else {  // the window leaves the history words: raster rows
           auto rbit = [&](int tau, uint32_t neuron) -> uint32_t {
@@ -987,7 +991,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
               const int tau = T - lag - d;
               if (tau < 0) break;
               if (rbit(tau, pre)) {
-                change += sa.ltp[lag];
+                change += tab_s[lag];
                 break;
               }
             }
@@ -996,7 +1000,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
             for (int lag = 1; lag <= sa.window; ++lag) {
               if (T - lag < 0) break;
               if (rbit(T - lag, post)) {
-                change -= sa.ltd[lag - 1];
+                change -= tab_s[16 + lag - 1];
                 break;
               }
             }
