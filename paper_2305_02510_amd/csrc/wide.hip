@@ -258,25 +258,31 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
     const int dbase = p * Dl;  // the phase's delays are dbase + 1 .. dbase + Dl
     const int rows = min(Dl, n.D - dbase);
     // stage the phase's rows: every load of a round is issued before its
-    // stores, so a round costs one memory latency, not one per word
+    // stores, so a round costs one memory latency, not one per word.  Word
+    // i of the phase is (row i / G, word i mod G); one division per round,
+    // then the next word of the thread (1024 further) by adding and carrying,
+    // and a word goes to LDS as one 8-byte store.
+    uint64_t* ring64 = reinterpret_cast<uint64_t*>(ring);
     for (int base = 0; base < rows * n.G; base += kWideThreads * kWideStage) {
       uint64_t v[kWideStage];
+      int r = (base + tid) / n.G, w = base + tid - r * n.G;
+      int at[kWideStage];  // the word's index r G + w in the staged rows
 #pragma unroll
       for (int q = 0; q < kWideStage; ++q) {
-        const int i = base + q * kWideThreads + tid;
-        const int r = i / n.G, w = i - r * n.G;
-        const int ts = t - (dbase + r + 1);
-        v[q] = (i < rows * n.G && ts >= 0) ? hist[static_cast<size_t>(ts) * rstride + w] : 0ull;
-      }
-#pragma unroll
-      for (int q = 0; q < kWideStage; ++q) {
-        const int i = base + q * kWideThreads + tid;
-        if (i < rows * n.G) {
-          const int r = i / n.G, w = i - r * n.G;
-          ring[r * W32 + 2 * w] = static_cast<uint32_t>(v[q]);
-          ring[r * W32 + 2 * w + 1] = static_cast<uint32_t>(v[q] >> 32);
+        if (q > 0) {
+          w += kWideThreads;
+          while (w >= n.G) {
+            w -= n.G;
+            ++r;
+          }
         }
+        const int ts = t - (dbase + r + 1);
+        at[q] = r * n.G + w;
+        v[q] = (r < rows && ts >= 0) ? hist[static_cast<size_t>(ts) * rstride + w] : 0ull;
       }
+#pragma unroll
+      for (int q = 0; q < kWideStage; ++q)
+        if (at[q] < rows * n.G) ring64[at[q]] = v[q];
     }
     __syncthreads();
 
