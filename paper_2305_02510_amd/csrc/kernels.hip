@@ -956,11 +956,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
     if (STDP && apply) {  // rule of step T = t - 1 on the loaded records
       const int T = t - 1;
       const uint64_t* hprev = sa.hist + static_cast<size_t>(T & 1) * n.Npad;
+      // the pre-neuron's history word is read only where the rule can need
+      // it: potentiation (the post spiked at T) or a delay whose pre spike of
+      // step T - d is not in the staged rows (depression otherwise reads
+      // that bit from the ring: row T - d = t - (d + 1))
       uint64_t hp[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool live = ok[u] && __float_as_uint(rr[u].w) != 0x80000000u;  // fillers keep -0.0
-        hp[u] = live ? hprev[rr[u].meta & 0xFFFFFu] : 0ull;
+        const int d = static_cast<int>((rr[u].meta >> 20) & 63u) + 1;
+        const bool need = (hq_s[rr[u].meta >> 26] & 1ull) || !RING || d >= n.D;
+        hp[u] = live && need ? hprev[rr[u].meta & 0xFFFFFu] : 0ull;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -976,7 +982,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_step(const DevNet n, int t, cons
             const uint32_t x = static_cast<uint32_t>(hp[u] >> d) & wmask;
             if (x) change += tab_s[__builtin_ctz(x)];
           }
-          if ((hp[u] >> d) & 1ull) {
+          const uint32_t pre_at = RING && d < n.D ? (ring[d * W32 + (pre >> 5)] >> (pre & 31u)) & 1u
+                                                  : static_cast<uint32_t>(hp[u] >> d) & 1u;
+          if (pre_at) {
             const uint32_t x = static_cast<uint32_t>(hq >> 1) & wmask;
             if (x) change -= tab_s[16 + __builtin_ctz(x)];
           }
