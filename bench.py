@@ -606,8 +606,8 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; how the simulation would shard "
-                                   "across GPUs is described in DESIGN.md but not built"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: sharding the simulation across GPUs "
+                                   "(post-neuron ranges with a per-step spike all-gather) is designed, not built"}))
         sys.exit(2)
 
     import torch
