@@ -443,6 +443,42 @@ def test_autotune_sparse_and_dense(gpu, oracle):
     assert_parity(dnet, dres, spikes, V, ref, f"autotuned dense {path}")
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_nets_every_path(gpu, oracle, seed):
+    """Random nets (sizes 40 .. 5000, densities, delays 1 .. 16, one to three
+    trials, heterogeneous parameters, some with hub posts) on every
+    single-net path and together in one batch, each against the oracle."""
+    from paper_2305_02510_amd import Batch
+    rng = np.random.default_rng(900 + seed)
+    nets = []
+    for i in range(6):
+        n = int(rng.integers(40, 5000))
+        net = wl.random_small(9000 + 10 * seed + i, n=n, p=float(min(0.2, rng.uniform(2, 40) / n)),
+                              max_delay=int(rng.integers(1, 17)), steps=80, trials=int(rng.integers(1, 4)),
+                              hetero=True)
+        if i % 3 == 2 and net.trials == 1:
+            net = _with_hubs(net, 9100 + i, hubs=2, extra=min(600, 4 * n))
+        nets.append(net)
+    refs = [oracle.run_sparse(net) for net in nets]
+    for net, res in zip(nets, refs):
+        for path in PATHS:
+            try:
+                s, V, r, used = simulate(gpu, net, path, chunks=[1, 30, 49])
+            except Exception as e:  # the single-workgroup path refuses nets that do not fit
+                assert path == "small" and "SN_ERANGE" in str(e), e
+                continue
+            assert_parity(net, res, s, V, r, f"{path} seed {seed}")
+    gs = [gpu.from_workload(net) for net in nets]
+    batch = Batch(gs)
+    batch.run(35)
+    batch.run(45)
+    for net, res, g in zip(nets, refs, gs):
+        assert_parity(net, res, g.read_raster(0, net.steps), *g.read_state(), f"batch seed {seed}")
+    batch.close()
+    for g in gs:
+        g.close()
+
+
 def test_batch_uneven(gpu, oracle):
     """Uneven batch of independent nets in one persistent launch: every net
     bit-exact against its own oracle run, resumed over two batch runs."""
@@ -482,11 +518,11 @@ def test_batch_with_trials_and_mixed_paths(gpu, oracle):
 
 
 def test_batch_compact_and_full_records(gpu, oracle):
-    """The batch kernel reads 4-byte record copies when every net allows them
-    (N <= 16384, delays <= 16, weights k * 2^-e with |k| <= 127) and the
-    8-byte records otherwise: a batch of compact nets, and the same batch
-    with one net whose weights need more (3.0 beside 1/64) and one with
-    delays up to 20."""
+    """The batch kernel reads 4-byte compact records when every net has them
+    (a spike ring of (D + 1) * 2G <= 2^13 words, weights k * 2^-e with
+    |k| <= 127) and the 8-byte records otherwise: a batch of compact nets,
+    and the same batch with one net whose weights need more (3.0 beside
+    1/64: no compact records) and one with delays up to 20."""
     from paper_2305_02510_amd import Batch
     base = [wl.random_small(3000 + i, n=[40, 300, 900][i % 3], p=0.08, max_delay=1 + i % 7, steps=70,
                             trials=1 + i % 2, hetero=True) for i in range(6)]
