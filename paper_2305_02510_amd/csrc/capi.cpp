@@ -275,6 +275,8 @@ sn_status check_status(sn_net* n) {
 // Launches steps t0 .. t0+steps-1 of a per-step path, through a cached HIP
 // graph when the run is long enough to amortise the capture.
 sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
+  // wide nets with lane records run two steps at a time (see launch_step_pair)
+  const bool pairs = path == SN_PATH_STEP && !n->stdp_on && step_pairs(n->d);
   auto launch_all = [&](hipStream_t s) -> hipError_t {
     for (int32_t k = 0; k < steps; ++k) {
       hipError_t e;
@@ -291,6 +293,9 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
         a.n = n->d;
         e = launch_step_stdp(a, t0 + k, k > 0 ? 1 : 0, s);
         if (e == hipSuccess && k == steps - 1) e = launch_stdp(a, t0 + k, s);
+      } else if (pairs && k + 1 < steps) {
+        e = launch_step_pair(n->d, t0 + k, s);  // steps t0 + k and t0 + k + 1
+        ++k;
       } else {
         e = launch_step(n->d, t0 + k, s);
       }
@@ -869,7 +874,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     }
     const WidePlan wp = wide_plan(n->d, cus);
     if (wp.P > 1) phase_rows = wp.Dl;
-    staged_all = wp.P > 1 || (wp.Dl >= n->d.D && wp.Dl > 0);
+    // lane records address the staged rows from LDS row 1
+    staged_all = (wp.P > 1 || (wp.Dl >= n->d.D && wp.Dl > 0)) && wp.shift == 1;
   }
   HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows);
   if (L.too_large)
@@ -883,16 +889,19 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   // 4-byte lane records, kept when it is at most 80% of the 8-byte records'
   // bytes
   std::vector<uint32_t> LR;
-  std::vector<int32_t> lgp, lws;
+  std::vector<int32_t> lgp, lws, lgs;
   float lscale = 0.f;
   if (staged_all && nnz > 0) {
     HostLayout LL = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows, true);
     if (!LL.too_large && LL.phases == L.phases && 4.0 * LL.recs.size() <= 0.8 * 8.0 * L.recs.size()) {
       LR = lane_records(LL, n->d.G, &lscale);
       if (!LR.empty()) {
-        LR.resize(LR.size() + static_cast<size_t>(kLaneBatchRows) * kGroup, 0u);  // slack of one batch
+        // slack of one batch of fillers (k = 0, a word of staged row 1)
+        const uint32_t row1 = 2u * static_cast<uint32_t>(n->d.G) * sizeof(uint32_t);
+        LR.resize(LR.size() + static_cast<size_t>(kLaneBatchRows) * kGroup, lane_record(0, row1, 0u));
         lgp = std::move(LL.gptr);
         lws = std::move(LL.wsec);
+        lgs = std::move(LL.gsplit);
       }
     }
   }
@@ -909,7 +918,12 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   void* wsec = L.phases > 1 ? dev_alloc(n, L.wsec.size() * sizeof(int32_t)) : nullptr;
   void* crecs = C.empty() ? nullptr : dev_alloc(n, C.size() * sizeof(uint32_t));
   void* lrecs = LR.empty() ? nullptr : dev_alloc(n, LR.size() * sizeof(uint32_t));
-  void* lgptr = LR.empty() ? nullptr : dev_alloc(n, lgp.size() * sizeof(int32_t));
+  // lane offsets: [G + 1] group starts, [G] delay-1 starts, then (256-byte
+  // aligned) the [B][Npad] input sums that the first kernel of a step pair
+  // leaves for the second
+  const size_t held_at = ((lgp.size() + lgs.size()) * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t lmeta_bytes = held_at + static_cast<size_t>(n->d.B) * n->d.Npad * sizeof(float);
+  void* lgptr = LR.empty() ? nullptr : dev_alloc(n, lmeta_bytes);
   void* lwsec = LR.empty() || L.phases <= 1 ? nullptr : dev_alloc(n, lws.size() * sizeof(int32_t));
   bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec) || (!C.empty() && !crecs) ||
              (!LR.empty() && (!lrecs || !lgptr || (L.phases > 1 && !lwsec)));
@@ -933,6 +947,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->d.lrecs = static_cast<const uint32_t*>(lrecs);
   n->d.lgptr = static_cast<const int32_t*>(lgptr);
   n->d.lwsec = static_cast<const int32_t*>(lwsec);
+  n->d.lgsplit = lgptr ? static_cast<const int32_t*>(lgptr) + lgp.size() : nullptr;
+  n->d.held = lgptr ? reinterpret_cast<float*>(static_cast<char*>(lgptr) + held_at) : nullptr;
   n->d.lscale = lscale;
   n->recs = recs;
   n->gptr = gptr;
@@ -965,6 +981,8 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   if (lrecs) {
     SN_HIP(n, hipMemcpyAsync(lrecs, LR.data(), LR.size() * sizeof(uint32_t), hipMemcpyHostToDevice, n->stream));
     SN_HIP(n, hipMemcpyAsync(lgptr, lgp.data(), lgp.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
+    SN_HIP(n, hipMemcpyAsync(static_cast<int32_t*>(lgptr) + lgp.size(), lgs.data(), lgs.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, n->stream));
     if (lwsec)
       SN_HIP(n, hipMemcpyAsync(lwsec, lws.data(), lws.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
   }
@@ -1084,6 +1102,8 @@ sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const i
     n->d.lrecs = nullptr;
     n->d.lgptr = nullptr;
     n->d.lwsec = nullptr;
+    n->d.lgsplit = nullptr;
+    n->d.held = nullptr;
     n->d.recs = nullptr;
     n->d.gptr = nullptr;
     n->d.gsplit = nullptr;

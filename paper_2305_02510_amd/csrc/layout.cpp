@@ -91,11 +91,7 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
     for (int sec = 0; sec <= P; ++sec) {
       const int part = sec == P ? 1 : 0;
       const int32_t ph = P - 1 - sec;  // phase of a part-A section
-      // lane_only (the wide kernel, which delivers phase 0 and the delay-1
-      // records together): the delay-1 records share phase 0's rows, and
-      // part B stays empty
-      const int32_t dmin = lane_only && ph == 0 ? 1 : 2;
-      const int32_t dlo = P > 1 ? std::max(dmin, ph * phase_rows + 1) : dmin;
+      const int32_t dlo = P > 1 ? std::max(2, ph * phase_rows + 1) : 2;
       const int32_t dhi = P > 1 ? (ph + 1) * phase_rows : 64;
       if (part == 1) L.gsplit[g] = static_cast<int32_t>(L.recs.size());
       else L.wsec[static_cast<size_t>(g) * P + ph] = static_cast<int32_t>(L.recs.size());
@@ -105,7 +101,7 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
         if (j < j1) {
           for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
             const int32_t dq = delay[order[q]];
-            if (part == 1 ? (dq == 1 && !lane_only) : (dq >= dlo && dq <= dhi)) lists[l].push_back(order[q]);
+            if (part == 1 ? dq == 1 : (dq >= dlo && dq <= dhi)) lists[l].push_back(order[q]);
           }
         }
         deg[l] = static_cast<int64_t>(lists[l].size());
@@ -188,7 +184,8 @@ std::vector<uint32_t> lane_records(const HostLayout& L, int32_t G, float* scale)
     if ((r.meta >> 26) != static_cast<uint32_t>(i % kGroup)) return {};  // not lane-owned
     const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
     const uint32_t pre = r.meta & 0xFFFFFu, d1 = (r.meta >> 20) & 63u;  // d1 = delay - 1
-    const uint32_t row = L.phase_rows > 0 ? d1 % static_cast<uint32_t>(L.phase_rows) : d1;
+    // row 0 of the staged rows holds the history one step later than row 1
+    const uint32_t row = (L.phase_rows > 0 ? d1 % static_cast<uint32_t>(L.phase_rows) : d1) + 1u;
     const uint64_t offset = (static_cast<uint64_t>(row) * W32 + (pre >> 5)) * 4u;
     if (offset >= kLaneMaxOffset) return {};
     out[i] = lane_record(k, static_cast<uint32_t>(offset), pre & 31u);

@@ -74,8 +74,7 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
 // phase_rows > 0 splits part A into delay phases of that many delays each
 // (see HostLayout), for nets of at least two phases; 0 = no phases.
 // lane_only: no overflow sections, every record in its post's lane (as many
-// rows as a section's largest in-degree), the delay-1 records in phase 0's
-// section (part B empty).
+// rows as a section's largest in-degree).
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
                         const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0, bool lane_only = false);
 
@@ -84,7 +83,10 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
 // are all k * 2^-e with |k| <= 127:
 //   bits 0..4    the source's bit in its 32-bit history word (pre mod 32)
 //   bits 5..22   LDS byte offset of that word among the phase's staged rows,
-//                (((delay - 1) mod phase_rows) * 2G + pre / 32) * 4
+//                (((delay - 1) mod phase_rows + 1) * 2G + pre / 32) * 4: row
+//                q >= 1 holds the history of step t - (first delay of the
+//                phase) - q + 1, and row 0 that of one step later, so the
+//                word one row below is the same source's word for step t + 1
 //   bits 24..31  k (int8)
 // A filler has k = 0.  The kernel reads batches of kLaneBatchRows rows and
 // skips the rows of a batch past its section's end (sections are whole
@@ -137,6 +139,8 @@ struct DevNet {
   const uint32_t* lrecs;
   const int32_t* lgptr;   // [G + 1]
   const int32_t* lwsec;   // [G][phases]
+  const int32_t* lgsplit; // [G] first delay-1 lane record of every group
+  float* held;            // [B][Npad] input of step t + 1 gathered by the first kernel of a step pair
   float lscale;
 };
 
@@ -311,17 +315,27 @@ std::vector<uint32_t> compact_records(const HostLayout& L, int32_t n, int32_t ma
 hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
 // Per-step kernel of nets whose D history rows do not fit in 64 KB of LDS
 // (wide.hip).  `grid` workgroups per trial own gpw groups each and stage Dl
-// history rows at a time in LDS; with P > 1 phases the layout orders part A
+// history rows at a time in LDS (plus the row of one step later for step
+// pairs); with P > 1 phases the layout orders part A
 // by delay phase so that every lookup is an LDS read (at most kWideMaxPhases
 // phases; otherwise P = 1 and delays above Dl read the raster in memory).
 constexpr int kWideMaxPhases = 4;
 struct WidePlan {
   int grid = 0, gpw = 0, Dl = 0, P = 1;
+  int shift = 1;  // 1: LDS row 0 kept for the row of one step later (step pairs, lane records)
 };
 bool wide_net(const DevNet& n);
 WidePlan wide_plan(const DevNet& n, int cus);
 hipError_t prepare_wide_kernel(const DevNet& n, int cus);
 hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s);
+// Steps t and t + 1 as one pass over the records of delay >= 2 (each such
+// record's source word for step t + 1 is one staged row below its word for
+// step t), then a short kernel for the delay-1 records of step t + 1 and its
+// update; for nets with lane records and n.held (step_pairs).
+bool step_pairs(const DevNet& n);
+hipError_t launch_step_pair(const DevNet& n, int32_t t, hipStream_t s);
+bool wide_pairs(const DevNet& n, int cus);
+hipError_t launch_pair_wide(const DevNet& n, int32_t t, int cus, hipStream_t s);
 hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_hist_build(const StdpArgs& a, int32_t t0, hipStream_t s);
 // per-step kernel with plasticity: applies the rule of step t - 1 when apply != 0

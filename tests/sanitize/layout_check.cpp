@@ -183,15 +183,27 @@ static void check_lane_layout(const Net& net, int32_t phase_rows) {
     for (int32_t i = L.gptr[g]; i < L.gptr[g + 1]; ++i) {
       const uint32_t c = LR[i];
       const int32_t k = L.src[i];
+      const uint32_t off = (c >> 5) & (kLaneMaxOffset - 1u);
       CHECK(static_cast<int32_t>(L.recs[i].meta >> 26) == (i - L.gptr[g]) % kGroup, "lane record %d off its lane", i);
+      // every record, filler or not, names a word of staged row 1 or below
+      // (the first kernel of a step pair also reads the word one row up)
+      CHECK(off >= 2u * G * 4u, "lane record %d: offset above row 1", i);
       if (k < 0) {
         CHECK((c >> 24) == 0, "filler %d: k", i);
         continue;
       }
       ++seen[k];
       const int32_t pre = net.pre[k], d = net.d[k];
-      const uint32_t row = P > 1 ? static_cast<uint32_t>((d - 1) % phase_rows) : static_cast<uint32_t>(d - 1);
-      const uint32_t off = (c >> 5) & (kLaneMaxOffset - 1u);
+      // delay 1 exactly in the last section, delays >= 2 of phase p in phase p's
+      size_t sec = 0;
+      while (bound[sec + 1] <= i) ++sec;
+      if (sec + 1 == bound.size() - 1) {
+        CHECK(d == 1, "lane record %d: delay %d in the delay-1 section", i, d);
+      } else {
+        const int32_t ph = P - 1 - static_cast<int32_t>(sec);
+        CHECK(d >= 2 && (P == 1 || (d - 1) / phase_rows == ph), "lane record %d: delay %d in phase %d", i, d, ph);
+      }
+      const uint32_t row = (P > 1 ? static_cast<uint32_t>((d - 1) % phase_rows) : static_cast<uint32_t>(d - 1)) + 1u;
       CHECK(off % 4 == 0 && off / 4 == row * 2u * G + static_cast<uint32_t>(pre) / 32u, "lane record %d: offset", i);
       CHECK((c & 31u) == static_cast<uint32_t>(pre) % 32u, "lane record %d: bit", i);
       const float wk = static_cast<float>(static_cast<int8_t>(c >> 24)) * scale;
