@@ -1271,19 +1271,6 @@ hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s) {
   return launch_step_t<1, 4, false>(n, t, none, 0, s);
 }
 
-bool step_pairs(const DevNet& n) {
-  if (step_ring_bytes(n) <= kStepRingLimit) return false;
-  int cus = 0;
-  if (device_cus(cus) != hipSuccess) return false;
-  return wide_pairs(n, cus);
-}
-
-hipError_t launch_step_pair(const DevNet& n, int32_t t, hipStream_t s) {
-  int cus = 0;
-  const hipError_t e = device_cus(cus);
-  return e != hipSuccess ? e : launch_pair_wide(n, t, cus, s);
-}
-
 hipError_t launch_step_stdp(const StdpArgs& a, int32_t t, int apply, hipStream_t s) {
   const DevNet& n = a.n;
   if (n.B != 1 || !a.hist) return hipErrorInvalidValue;

@@ -627,4 +627,25 @@ hipError_t launch_pair_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) 
   return hipGetLastError();
 }
 
+static hipError_t device_cus_wide(int& cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return e;
+}
+
+// the per-step path of a net runs this kernel exactly when wide_net holds
+bool step_pairs(const DevNet& n) {
+  if (!wide_net(n)) return false;
+  int cus = 0;
+  if (device_cus_wide(cus) != hipSuccess) return false;
+  return wide_pairs(n, cus);
+}
+
+hipError_t launch_step_pair(const DevNet& n, int32_t t, hipStream_t s) {
+  int cus = 0;
+  const hipError_t e = device_cus_wide(cus);
+  return e != hipSuccess ? e : launch_pair_wide(n, t, cus, s);
+}
+
 }  // namespace snmi

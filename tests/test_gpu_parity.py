@@ -206,7 +206,9 @@ def test_wide_step_lane_records(gpu, oracle, n, p, D, trials):
     """The wide per-step kernel on 4-byte lane records (every post's synapses
     in its lane, no hub: the lane-only copy is kept): two delay phases with
     2 trials; every delay staged at once; more than 16 groups per workgroup
-    (each wave owns groups) with two phases; empty sections throughout."""
+    (each wave owns groups) with two phases; empty sections throughout.
+    Runs of 1, 40 and 49 steps: a single step, step pairs, and pairs
+    followed by a single step."""
     net = wl.large_sparse(60 + D, n=n, p=p, steps=90, max_delay=D)
     net = _with_gaps(dataclasses.replace(net, trials=trials, ext=np.concatenate([net.ext] * trials)))
     if trials > 1:
