@@ -3,7 +3,8 @@
 // synaptic input of §2.1's update summed over the pull records of every
 // post-neuron group, followed by the fused neuron update.
 //
-// One launch per step.  Workgroup (w, b) owns the contiguous groups
+// One launch per step, or two per step pair (see MODE below: records of
+// delay >= 2 read once for two steps).  Workgroup (w, b) owns the contiguous groups
 // [g0, g1) of trial b.  The delays are cut into phases of Dl delays (Dl =
 // as many history rows as fit in LDS beside the sums); the layout orders the
 // delay >= 2 records of every group by phase (phases P-1 .. 1, then phase 0
@@ -29,10 +30,11 @@
 // ... and writes their spike words.
 //
 // LANE: when every delay is staged (phases cover D) the net may also hold a
-// lane-only copy of its layout (no overflow: every record in its post's lane)
+// lane-only copy of its layout (no overflow: every record in its post's lane;
+// the delay-1 records in a section of their own after the phases)
 // as 4-byte lane records that carry the LDS offset of their source word, the
-// source's bit and an int8 weight numerator, with every section padded to
-// whole batches.  The kernel then streams those, half the bytes of the
+// source's bit and an int8 weight numerator, every section whole rows of
+// 64.  The kernel then streams those, half the bytes of the
 // 8-byte records, with no atomic, no bounds mask and no address arithmetic
 // beyond two bit-field extractions per record; a lane sums its numerators as
 // an integer and scales the sum once.
