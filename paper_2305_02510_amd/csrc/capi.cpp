@@ -275,8 +275,8 @@ sn_status check_status(sn_net* n) {
 // Launches steps t0 .. t0+steps-1 of a per-step path, through a cached HIP
 // graph when the run is long enough to amortise the capture.
 sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
-  // wide nets with lane records run two steps at a time (see launch_step_pair)
-  const bool pairs = path == SN_PATH_STEP && !n->stdp_on && step_pairs(n->d);
+  // wide nets with lane records run blocks of steps (see launch_step_block)
+  const int32_t blk = path == SN_PATH_STEP && !n->stdp_on ? step_block(n->d) : 1;
   auto launch_all = [&](hipStream_t s) -> hipError_t {
     for (int32_t k = 0; k < steps; ++k) {
       hipError_t e;
@@ -293,9 +293,9 @@ sn_status run_per_step(sn_net* n, int32_t path, int32_t t0, int32_t steps) {
         a.n = n->d;
         e = launch_step_stdp(a, t0 + k, k > 0 ? 1 : 0, s);
         if (e == hipSuccess && k == steps - 1) e = launch_stdp(a, t0 + k, s);
-      } else if (pairs && k + 1 < steps) {
-        e = launch_step_pair(n->d, t0 + k, s);  // steps t0 + k and t0 + k + 1
-        ++k;
+      } else if (blk > 1 && k + blk <= steps) {
+        e = launch_step_block(n->d, t0 + k, s);  // steps t0 + k .. t0 + k + blk - 1
+        k += blk - 1;
       } else {
         e = launch_step(n->d, t0 + k, s);
       }
@@ -866,6 +866,7 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   // records ordered by delay phase for the wide kernel (wide.hip)
   int32_t phase_rows = 0;
   bool staged_all = false;  // every delay's history row staged in LDS by the wide kernel
+  int32_t lane_block = 1;   // steps per block of the wide kernel's lane layout
   if (wide_net(n->d)) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, n->device) != hipSuccess) {
@@ -874,8 +875,9 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
     }
     const WidePlan wp = wide_plan(n->d, cus);
     if (wp.P > 1) phase_rows = wp.Dl;
-    // lane records address the staged rows from LDS row 1
-    staged_all = (wp.P > 1 || (wp.Dl >= n->d.D && wp.Dl > 0)) && wp.shift == 1;
+    // lane records address the staged rows of a block of steps
+    staged_all = (wp.P > 1 || (wp.Dl >= n->d.D && wp.Dl > 0)) && wp.block >= 2;
+    lane_block = wp.block;
   }
   HostLayout L = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows);
   if (L.too_large)
@@ -889,19 +891,20 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   // 4-byte lane records, kept when it is at most 80% of the 8-byte records'
   // bytes
   std::vector<uint32_t> LR;
-  std::vector<int32_t> lgp, lws, lgs;
+  std::vector<int32_t> lgp, lws, lss;
   float lscale = 0.f;
   if (staged_all && nnz > 0) {
-    HostLayout LL = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows, true);
+    HostLayout LL = build_layout(n->d.N, nnz, pre, post, w, delay, n->d.D, phase_rows, true, lane_block);
     if (!LL.too_large && LL.phases == L.phases && 4.0 * LL.recs.size() <= 0.8 * 8.0 * L.recs.size()) {
       LR = lane_records(LL, n->d.G, &lscale);
       if (!LR.empty()) {
-        // slack of one batch of fillers (k = 0, a word of staged row 1)
-        const uint32_t row1 = 2u * static_cast<uint32_t>(n->d.G) * sizeof(uint32_t);
+        // slack of one batch of fillers (k = 0, a word of the row of delay 1)
+        const uint32_t row1 = static_cast<uint32_t>(lane_block - 1) * 2u * static_cast<uint32_t>(n->d.G) *
+                              sizeof(uint32_t);
         LR.resize(LR.size() + static_cast<size_t>(kLaneBatchRows) * kGroup, lane_record(0, row1, 0u));
         lgp = std::move(LL.gptr);
         lws = std::move(LL.wsec);
-        lgs = std::move(LL.gsplit);
+        lss = std::move(LL.ssec);
       }
     }
   }
@@ -918,11 +921,12 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   void* wsec = L.phases > 1 ? dev_alloc(n, L.wsec.size() * sizeof(int32_t)) : nullptr;
   void* crecs = C.empty() ? nullptr : dev_alloc(n, C.size() * sizeof(uint32_t));
   void* lrecs = LR.empty() ? nullptr : dev_alloc(n, LR.size() * sizeof(uint32_t));
-  // lane offsets: [G + 1] group starts, [G] delay-1 starts, then (256-byte
-  // aligned) the [B][Npad] input sums that the first kernel of a step pair
-  // leaves for the second
-  const size_t held_at = ((lgp.size() + lgs.size()) * sizeof(int32_t) + 255) / 256 * 256;
-  const size_t lmeta_bytes = held_at + static_cast<size_t>(n->d.B) * n->d.Npad * sizeof(float);
+  // lane offsets: [G + 1] group starts, [G][block - 1] starts of the short
+  // delays' sections, then (256-byte aligned) the [block - 1][B][Npad] input
+  // sums that the first kernel of a block of steps leaves for the later ones
+  const size_t held_at = ((lgp.size() + lss.size()) * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t lmeta_bytes =
+      held_at + static_cast<size_t>(lane_block - 1) * n->d.B * n->d.Npad * sizeof(float);
   void* lgptr = LR.empty() ? nullptr : dev_alloc(n, lmeta_bytes);
   void* lwsec = LR.empty() || L.phases <= 1 ? nullptr : dev_alloc(n, lws.size() * sizeof(int32_t));
   bool bad = !recs || !gptr || !gsplit || !orecs || !optr || (L.phases > 1 && !wsec) || (!C.empty() && !crecs) ||
@@ -947,8 +951,9 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   n->d.lrecs = static_cast<const uint32_t*>(lrecs);
   n->d.lgptr = static_cast<const int32_t*>(lgptr);
   n->d.lwsec = static_cast<const int32_t*>(lwsec);
-  n->d.lgsplit = lgptr ? static_cast<const int32_t*>(lgptr) + lgp.size() : nullptr;
+  n->d.lsec = lgptr ? static_cast<const int32_t*>(lgptr) + lgp.size() : nullptr;
   n->d.held = lgptr ? reinterpret_cast<float*>(static_cast<char*>(lgptr) + held_at) : nullptr;
+  n->d.lblock = lgptr ? lane_block : 0;
   n->d.lscale = lscale;
   n->recs = recs;
   n->gptr = gptr;
@@ -981,7 +986,7 @@ sn_status sn_load_weights_delays(sn_net* n, int64_t nnz, const int32_t* pre, con
   if (lrecs) {
     SN_HIP(n, hipMemcpyAsync(lrecs, LR.data(), LR.size() * sizeof(uint32_t), hipMemcpyHostToDevice, n->stream));
     SN_HIP(n, hipMemcpyAsync(lgptr, lgp.data(), lgp.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
-    SN_HIP(n, hipMemcpyAsync(static_cast<int32_t*>(lgptr) + lgp.size(), lgs.data(), lgs.size() * sizeof(int32_t),
+    SN_HIP(n, hipMemcpyAsync(static_cast<int32_t*>(lgptr) + lgp.size(), lss.data(), lss.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, n->stream));
     if (lwsec)
       SN_HIP(n, hipMemcpyAsync(lwsec, lws.data(), lws.size() * sizeof(int32_t), hipMemcpyHostToDevice, n->stream));
@@ -1102,8 +1107,9 @@ sn_status sn_load_dense_rows_i8(sn_net* n, int32_t row0, int32_t n_rows, const i
     n->d.lrecs = nullptr;
     n->d.lgptr = nullptr;
     n->d.lwsec = nullptr;
-    n->d.lgsplit = nullptr;
+    n->d.lsec = nullptr;
     n->d.held = nullptr;
+    n->d.lblock = 0;
     n->d.recs = nullptr;
     n->d.gptr = nullptr;
     n->d.gsplit = nullptr;

@@ -53,7 +53,7 @@ int64_t lane_rows(const std::vector<int64_t>& deg) {
 }  // namespace
 
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
-                        const uint8_t* delay, int32_t max_delay, int32_t phase_rows, bool lane_only) {
+                        const uint8_t* delay, int32_t max_delay, int32_t phase_rows, bool lane_only, int32_t block) {
   HostLayout L;
   // delay phases (phase p: delays p * phase_rows + 1 .. (p + 1) * phase_rows);
   // part A holds the sections of phases P-1 .. 1, then phase 0 (delays >= 2)
@@ -81,33 +81,41 @@ HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_
   L.gptr.assign(static_cast<size_t>(G) + 1, 0);
   L.gsplit.assign(static_cast<size_t>(G), 0);
   L.wsec.assign(static_cast<size_t>(G) * P, 0);
+  L.block = block;
+  L.ssec.assign(static_cast<size_t>(G) * (block - 1), 0);
   std::vector<std::vector<int64_t>> lists(kGroup);
   std::vector<int64_t> deg(kGroup);
   for (int32_t g = 0; g < G; ++g) {
     L.gptr[g] = static_cast<int32_t>(L.recs.size());
     const int32_t j0 = g * kGroup;
     const int32_t j1 = std::min(n, j0 + kGroup);
-    // sections: phases P-1 .. 0 of part A (delay >= 2), then part B (delay 1)
-    for (int sec = 0; sec <= P; ++sec) {
-      const int part = sec == P ? 1 : 0;
+    // sections: phases P-1 .. 0 of part A (delay >= block), then the short
+    // delays block - 1 .. 1 (block 2: part B, delay 1)
+    for (int sec = 0; sec < P + block - 1; ++sec) {
+      const int part = sec >= P ? 1 : 0;
       const int32_t ph = P - 1 - sec;  // phase of a part-A section
-      const int32_t dlo = P > 1 ? std::max(2, ph * phase_rows + 1) : 2;
-      const int32_t dhi = P > 1 ? (ph + 1) * phase_rows : 64;
-      if (part == 1) L.gsplit[g] = static_cast<int32_t>(L.recs.size());
-      else L.wsec[static_cast<size_t>(g) * P + ph] = static_cast<int32_t>(L.recs.size());
+      const int32_t dshort = P + block - 1 - sec;  // delay of a short section
+      const int32_t dlo = part == 1 ? dshort : P > 1 ? std::max(block, ph * phase_rows + 1) : block;
+      const int32_t dhi = part == 1 ? dshort : P > 1 ? (ph + 1) * phase_rows : 64;
+      if (part == 1) {
+        L.ssec[static_cast<size_t>(g) * (block - 1) + dshort - 1] = static_cast<int32_t>(L.recs.size());
+        if (dshort == 1) L.gsplit[g] = static_cast<int32_t>(L.recs.size());
+      } else {
+        L.wsec[static_cast<size_t>(g) * P + ph] = static_cast<int32_t>(L.recs.size());
+      }
       for (int l = 0; l < kGroup; ++l) {
         lists[l].clear();
         const int32_t j = j0 + l;
         if (j < j1) {
           for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
             const int32_t dq = delay[order[q]];
-            if (part == 1 ? dq == 1 : (dq >= dlo && dq <= dhi)) lists[l].push_back(order[q]);
+            if (dq >= dlo && dq <= dhi) lists[l].push_back(order[q]);
           }
         }
         deg[l] = static_cast<int64_t>(lists[l].size());
       }
       // a filler names neuron 0 with a delay of this section and weight -0
-      const uint32_t fill_delay = part == 0 ? static_cast<uint32_t>(dlo) : 1u;
+      const uint32_t fill_delay = static_cast<uint32_t>(dlo);
       int64_t R = lane_rows(deg);
       if (lane_only)  // every synapse in its post's lane: as many rows as the largest in-degree
         for (int l = 0; l < kGroup; ++l) R = std::max(R, deg[l]);
@@ -184,8 +192,9 @@ std::vector<uint32_t> lane_records(const HostLayout& L, int32_t G, float* scale)
     if ((r.meta >> 26) != static_cast<uint32_t>(i % kGroup)) return {};  // not lane-owned
     const int32_t k = static_cast<int32_t>(r.w * f);  // exact: an integer of magnitude <= 127
     const uint32_t pre = r.meta & 0xFFFFFu, d1 = (r.meta >> 20) & 63u;  // d1 = delay - 1
-    // row 0 of the staged rows holds the history one step later than row 1
-    const uint32_t row = (L.phase_rows > 0 ? d1 % static_cast<uint32_t>(L.phase_rows) : d1) + 1u;
+    // rows 0 .. block - 2 of the staged rows hold the history of later steps
+    const uint32_t row = (L.phase_rows > 0 ? d1 % static_cast<uint32_t>(L.phase_rows) : d1) +
+                         static_cast<uint32_t>(L.block - 1);
     const uint64_t offset = (static_cast<uint64_t>(row) * W32 + (pre >> 5)) * 4u;
     if (offset >= kLaneMaxOffset) return {};
     out[i] = lane_record(k, static_cast<uint32_t>(offset), pre & 31u);

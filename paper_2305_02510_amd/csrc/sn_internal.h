@@ -42,6 +42,11 @@ struct HostLayout {
   std::vector<int32_t> src;     // input index of every record, -1 for fillers
   std::vector<int32_t> gptr;    // [G + 1] record offset of every group
   std::vector<int32_t> gsplit;  // [G] first delay-1 record of every group
+  // short sections (block > 2): ssec[g * (block - 1) + d - 1] is the first
+  // record of group g's section of delay d, d = 1 .. block - 1 (the sections
+  // follow phase 0 in the order d = block - 1 .. 1; ssec of d = 1 = gsplit)
+  int32_t block = 2;
+  std::vector<int32_t> ssec;  // [G][block - 1]
   int32_t max_group_records = 0;
   // set when the records with fillers would pass INT32_MAX (offsets are
   // 32-bit on the device); the other fields are then incomplete
@@ -74,19 +79,22 @@ SlicePlan partition_groups(const HostLayout& L, int32_t G, int32_t slices, int32
 // phase_rows > 0 splits part A into delay phases of that many delays each
 // (see HostLayout), for nets of at least two phases; 0 = no phases.
 // lane_only: no overflow sections, every record in its post's lane (as many
-// rows as a section's largest in-degree).
+// rows as a section's largest in-degree).  block >= 2: part A holds the
+// delays >= block, and the delays 1 .. block - 1 get a section each after it
+// (block 2: part B, the delay-1 records); needs phase_rows >= block - 1.
 HostLayout build_layout(int32_t n, int64_t nnz, const int32_t* pre, const int32_t* post, const float* w,
-                        const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0, bool lane_only = false);
+                        const uint8_t* delay, int32_t max_delay = 64, int32_t phase_rows = 0, bool lane_only = false,
+                        int32_t block = 2);
 
 // Lane record, 4 bytes, of a lane_only layout (the post is the lane) for the
 // wide per-step kernel when every delay is staged in LDS, nets whose weights
 // are all k * 2^-e with |k| <= 127:
 //   bits 0..4    the source's bit in its 32-bit history word (pre mod 32)
 //   bits 5..22   LDS byte offset of that word among the phase's staged rows,
-//                (((delay - 1) mod phase_rows + 1) * 2G + pre / 32) * 4: row
-//                q >= 1 holds the history of step t - (first delay of the
-//                phase) - q + 1, and row 0 that of one step later, so the
-//                word one row below is the same source's word for step t + 1
+//                (((delay - 1) mod phase_rows + block - 1) * 2G + pre / 32) * 4:
+//                LDS row r holds the history of step t - (first delay of the
+//                phase) - r + block - 2, so the word i rows below is the same
+//                source's word for step t + i (blocks of steps)
 //   bits 24..31  k (int8)
 // A filler has k = 0.  The kernel reads batches of kLaneBatchRows rows and
 // skips the rows of a batch past its section's end (sections are whole
@@ -98,9 +106,9 @@ __host__ __device__ inline uint32_t lane_record(int32_t k, uint32_t byte_offset,
   return (static_cast<uint32_t>(k) << 24) | (byte_offset << 5) | bit;
 }
 // Lane records of a lane_only layout for G groups and the layout's phases
-// (phase_rows = 0: no phases, every delay staged at once), or empty when a
-// record is not in its post's lane, a weight does not allow it or an offset
-// does not fit; *scale = 2^-e.
+// and block (phase_rows = 0: no phases, every delay staged at once), or empty
+// when a record is not in its post's lane, a weight does not allow it or an
+// offset does not fit; *scale = 2^-e.
 std::vector<uint32_t> lane_records(const HostLayout& L, int32_t G, float* scale);
 
 // Plain pointers and sizes handed to every kernel.
@@ -139,8 +147,9 @@ struct DevNet {
   const uint32_t* lrecs;
   const int32_t* lgptr;   // [G + 1]
   const int32_t* lwsec;   // [G][phases]
-  const int32_t* lgsplit; // [G] first delay-1 lane record of every group
-  float* held;            // [B][Npad] input of step t + 1 gathered by the first kernel of a step pair
+  const int32_t* lsec;    // [G][lblock - 1] first lane record of the section of delay d (index d - 1)
+  float* held;            // [lblock - 1][B][Npad] input of steps t + 1 .. gathered by a block's first kernel
+  int32_t lblock;         // steps per block of the lane layout (2 or 4)
   float lscale;
 };
 
@@ -322,20 +331,23 @@ hipError_t launch_step(const DevNet& n, int32_t t, hipStream_t s);
 constexpr int kWideMaxPhases = 4;
 struct WidePlan {
   int grid = 0, gpw = 0, Dl = 0, P = 1;
-  int shift = 1;  // 1: LDS row 0 kept for the row of one step later (step pairs, lane records)
+  int block = 1;  // steps per block (lane records): 4, 2, or 1 (no extra rows)
+  int shift = 0;  // block - 1: LDS rows kept for the rows of later steps
 };
 bool wide_net(const DevNet& n);
 WidePlan wide_plan(const DevNet& n, int cus);
 hipError_t prepare_wide_kernel(const DevNet& n, int cus);
 hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s);
-// Steps t and t + 1 as one pass over the records of delay >= 2 (each such
-// record's source word for step t + 1 is one staged row below its word for
-// step t), then a short kernel for the delay-1 records of step t + 1 and its
-// update; for nets with lane records and n.held (step_pairs).
-bool step_pairs(const DevNet& n);
-hipError_t launch_step_pair(const DevNet& n, int32_t t, hipStream_t s);
-bool wide_pairs(const DevNet& n, int cus);
-hipError_t launch_pair_wide(const DevNet& n, int32_t t, int cus, hipStream_t s);
+// A block of K = step_block(n) > 1 steps t .. t + K - 1 (wide nets with
+// lane records and n.held): one pass over every record, a record of delay d
+// adding into steps t .. t + min(d, K) - 1 (its source word for step t + i
+// is i staged rows below its word for step t), then for i = 1 .. K - 1 a
+// short kernel that adds the records of delays 1 .. i to step t + i and
+// updates it.  1: no blocks.
+int step_block(const DevNet& n);
+hipError_t launch_step_block(const DevNet& n, int32_t t, hipStream_t s);
+int wide_block(const DevNet& n, int cus);
+hipError_t launch_block_wide(const DevNet& n, int32_t t, int cus, hipStream_t s);
 hipError_t launch_stdp(const StdpArgs& a, int32_t t, hipStream_t s);
 hipError_t launch_hist_build(const StdpArgs& a, int32_t t0, hipStream_t s);
 // per-step kernel with plasticity: applies the rule of step t - 1 when apply != 0

@@ -66,26 +66,40 @@ __device__ __forceinline__ void wide_load(const DevNet& n, int base, int end, in
 }
 
 // Records of group g in phase p: phase p >= 1 is the section [wsec[p],
-// wsec[p - 1]); phase 0 runs from wsec[0] to the group's end (delay-1 part
-// included).  Without phases: all records of the group.  LANE: the offsets of
-// the lane-record layout, and `sec` picks part of it: 0 the whole phase as
-// above, 1 the phase's records of delay >= 2 (phase 0 ends where the group's
-// delay-1 records begin), 2 the group's delay-1 records.
+// wsec[p - 1]); phase 0 runs from wsec[0] to the group's end (the short
+// sections included).  Without phases: all records of the group.  LANE: the
+// offsets of the lane-record layout, and the section kind: kSecPhase as
+// above; kSecLong phase p's delays >= block (phase 0 ends where the short
+// sections begin); kSecShort the section of delay d < block; kSecFrom the
+// sections of delays d .. 1 (from the section of delay d to the group's end).
+constexpr int kSecPhase = 0, kSecLong = 1, kSecShort = 2, kSecFrom = 3;
 template <bool LANE>
-__device__ __forceinline__ void wide_range(const DevNet& n, int g, int p, int sec, int& beg, int& end) {
-  const int32_t* gp = LANE ? n.lgptr : n.gptr;
-  if (LANE && sec == 2) {
-    beg = n.lgsplit[g];
-    end = gp[g + 1];
+__device__ __forceinline__ void wide_range(const DevNet& n, int g, int p, int kind, int d, int& beg, int& end) {
+    if (!LANE) {
+    if (n.phases <= 1) {
+      beg = n.gptr[g];
+      end = n.gptr[g + 1];
+      return;
+    }
+    const int32_t* ws = n.wsec + static_cast<size_t>(g) * n.phases;
+    beg = ws[p];
+    end = p == 0 ? n.gptr[g + 1] : ws[p - 1];
     return;
   }
-  const int32_t last = LANE && sec == 1 ? n.lgsplit[g] : gp[g + 1];  // end of phase 0
+  const int32_t* lg = n.lgptr;
+  const int32_t* ss = n.lsec + static_cast<size_t>(g) * (n.lblock - 1);  // ss[d - 1]: section of delay d
+  if (kind == kSecShort || kind == kSecFrom) {
+    beg = ss[d - 1];
+    end = kind == kSecFrom || d == 1 ? lg[g + 1] : ss[d - 2];
+    return;
+  }
+  const int32_t last = kind == kSecLong ? ss[n.lblock - 2] : lg[g + 1];  // end of phase 0
   if (n.phases <= 1) {
-    beg = gp[g];
+    beg = lg[g];
     end = last;
     return;
   }
-  const int32_t* ws = (LANE ? n.lwsec : n.wsec) + static_cast<size_t>(g) * n.phases;
+  const int32_t* ws = n.lwsec + static_cast<size_t>(g) * n.phases;
   beg = ws[p];
   end = p == 0 ? last : ws[p - 1];
 }
@@ -101,7 +115,7 @@ struct WidePair {
 
 __device__ __forceinline__ void wide_enter(const DevNet& n, WidePair& s, int p) {
   constexpr int batch = 64 * kWideU;
-  wide_range<false>(n, s.g, p, 0, s.beg, s.end);
+  wide_range<false>(n, s.g, p, kSecPhase, 0, s.beg, s.end);
   s.nb = max(1, (s.end - s.beg + batch - 1) / batch);
 }
 
@@ -152,8 +166,9 @@ struct LanePair {
   bool valid;
 };
 
+// sec = kind * 64 + d (see wide_range)
 __device__ __forceinline__ void lane_enter(const DevNet& n, LanePair& s, int p, int sec) {
-  wide_range<true>(n, s.g, p, sec, s.beg, s.end);
+  wide_range<true>(n, s.g, p, sec >> 6, sec & 63, s.beg, s.end);
   s.nb = (s.end - s.beg + 64 * kLaneU - 1) / (64 * kLaneU);
 }
 
@@ -210,18 +225,20 @@ __device__ __forceinline__ void lane_load(const DevNet& n, const LanePair& s, in
 }
 
 // One wave's walk over the lane records of section `sec` of phase p (see
-// wide_range): no barrier, three record buffers in rotation keep two batches
+// lane_enter): no barrier, three record buffers in rotation keep two batches
 // in flight while one is delivered (no buffer is copied: a copy would wait
 // for its load).  A lane sums the weight numerators k of its active records
-// as an integer; DUAL (records of delay >= 2 in the first kernel of a step
-// pair) also sums, into isum2, the records whose source spiked one step
-// later: the word one staged row below.  An owned group's sums go to its
-// LDS rows (gacc, gacc2) when the walk leaves it; a team member keeps its
-// share in isum / isum2.
-template <bool DUAL>
+// as integers: for C steps of a block at once (the first kernel of a block,
+// records of delay >= C), sum j from the source word j staged rows below the
+// record's word, j = 0 .. C - 1, after skipping `skip` bytes of rows (the
+// later kernels of a block).  An owned group's sums go to its LDS rows (sum
+// j at gacc + j * gstride) when the walk leaves it; a team member keeps its
+// share in isum.
+template <int C, int NS>
 __device__ __forceinline__ void lane_walk(const DevNet& n, int p, int sec, int g0, int g1, bool own, int team,
                                           int member, int m, int lane, const char* ring_bytes, uint32_t row_bytes,
-                                          float* gacc, float* gacc2, int& isum, int& isum2) {
+                                          uint32_t skip, float* gacc, int gstride, int (&isum)[NS]) {
+  static_assert(C <= NS, "one sum per step");
   LanePair s0 = lane_start(n, p, sec, g0, g1, own, team, member);
   LanePair s1 = lane_next(n, s0, p, sec, g1, m, own), s2 = lane_next(n, s1, p, sec, g1, m, own);
   uint32_t b0[kLaneU], b1[kLaneU], b2[kLaneU];
@@ -231,15 +248,16 @@ __device__ __forceinline__ void lane_walk(const DevNet& n, int p, int sec, int g
   auto body = [&](const LanePair& sc, const uint32_t (&cur)[kLaneU], const LanePair& sn) -> bool {
     if (!sc.valid) return false;
     auto deliver = [&](uint32_t c) {
-      const uint32_t off = (c >> 5) & (kLaneMaxOffset - 1u);
+      // every record of these sections lies at least skip + (C - 1) rows
+      // below row 0 (its row is (d - 1) mod Dl + block - 1)
+      const uint32_t off = ((c >> 5) & (kLaneMaxOffset - 1u)) - skip;
       const int k = static_cast<int>(c) >> 24;
-      const uint32_t word = *reinterpret_cast<const uint32_t*>(ring_bytes + off);
-      // all ones when the source spiked (the bit sign-extended), else 0
-      // (v_bfe reads only the offset's low 5 bits: the source's bit)
-      isum += __builtin_amdgcn_sbfe(static_cast<int>(word), c, 1u) & k;
-      if constexpr (DUAL) {  // every record here lies in row 1 or below: off >= row_bytes
-        const uint32_t word2 = *reinterpret_cast<const uint32_t*>(ring_bytes + (off - row_bytes));
-        isum2 += __builtin_amdgcn_sbfe(static_cast<int>(word2), c, 1u) & k;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const uint32_t word = *reinterpret_cast<const uint32_t*>(ring_bytes + (off - j * row_bytes));
+        // all ones when the source spiked (the bit sign-extended), else 0
+        // (v_bfe reads only the offset's low 5 bits: the source's bit)
+        isum[j] += __builtin_amdgcn_sbfe(static_cast<int>(word), c, 1u) & k;
       }
     };
     const int rows_left = (sc.end - sc.beg) / 64 - sc.k * kLaneU;  // uniform
@@ -252,11 +270,10 @@ __device__ __forceinline__ void lane_walk(const DevNet& n, int p, int sec, int g
         if (u < rows_left) deliver(cur[u]);
     }
     if (own && (!sn.valid || sn.g != sc.g)) {  // an owned group: this wave is its only contributor
-      gacc[(sc.g - g0) * kGroup + lane] += static_cast<float>(isum) * n.lscale;
-      isum = 0;
-      if constexpr (DUAL) {
-        gacc2[(sc.g - g0) * kGroup + lane] += static_cast<float>(isum2) * n.lscale;
-        isum2 = 0;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        gacc[j * gstride + (sc.g - g0) * kGroup + lane] += static_cast<float>(isum[j]) * n.lscale;
+        isum[j] = 0;
       }
     }
     return sn.valid;
@@ -280,22 +297,27 @@ __device__ __forceinline__ void lane_walk(const DevNet& n, int p, int sec, int g
 // FALLBACK: no delay phases and more delays than staged rows; delays above
 // the staged rows read the raster in memory.
 // NPW: groups one wave updates at most (1 when a workgroup has <= 16).
-// LANE: lane records (n.lrecs, n.lgptr, n.lwsec); never with FALLBACK.
-// MODE 0: step t.  MODE 1 and 2 (LANE only): steps t and t + 1 of a step
-// pair.  MODE 1 delivers step t and, from the same records of delay >= 2
-// (their sources' words one staged row below), the input of step t + 1 from
-// those delays, which it leaves in n.held; MODE 2, launched for step t + 1,
-// adds the delay-1 records to n.held and updates.  A record of delay d >= 2
-// is then read once for the two steps.
-// Row q of a phase (first delay dbase + 1) holds the history of step
-// t - dbase - q, at LDS row q - 1 + shift: rows q = 1 .. rows always, q = 0
-// for MODE 1 in phases p >= 1.  shift = 1 (whenever lane records exist) also
-// keeps the second step's sums and team slots; shift = 0 only when they and
-// a second row do not fit (then LDS holds one step's sums).
-template <bool FALLBACK, int NPW, bool LANE, int MODE>
-__global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int t, int Dl, int P, int shift) {
+// LANE: lane records (n.lrecs, n.lgptr, n.lwsec, n.lsec); never with FALLBACK.
+// MODE 0: step t.  MODE 1 and 2 (LANE only): a block of KT = n.lblock steps
+// t .. t + KT - 1.  The input of step t + i through a synapse of delay d > i
+// depends only on spikes up to step t - 1.  MODE 1 streams every record once:
+// a record of delay d adds into the sums of steps t .. t + min(d, KT) - 1
+// (its source words 0 .. min(d, KT) - 1 staged rows below its word); it
+// updates step t and leaves the sums of steps t + 1 .. in n.held.  MODE 2,
+// launched for i = 1 .. KT - 1 in turn, adds the records of delays 1 .. i to
+// step t + i's held sum and updates step t + i.
+// LDS row r of a phase (first delay dbase + 1) holds the history of step
+// t - dbase - r + shift - 1 (shift = block - 1 extra rows, 0 when a single
+// history row fills the LDS): MODE 0 stages the rows of steps t - dbase - 1
+// .. t - dbase - rows; MODE 1 in phases p >= 1 also the shift later ones
+// (all before step t while Dl >= block - 1); MODE 2 (phase 0) the rows of
+// steps t .. t + i - 1.  After the rows: the sums of the block's steps
+// [shift + 1][g1 - g0][64], then the team slots [shift + 1][16][64].
+template <bool FALLBACK, int NPW, bool LANE, int MODE, int KT>
+__global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int t, int Dl, int P, int shift, int ib) {
   constexpr int U = kWideU;
-  static_assert(MODE == 0 || (LANE && !FALLBACK), "step pairs run on lane records");
+  constexpr int NS = MODE == 1 ? KT : 1;  // sums per lane
+  static_assert(MODE == 0 || (LANE && !FALLBACK), "blocks of steps run on lane records");
   extern __shared__ __align__(16) uint32_t smem[];
   const int b = blockIdx.y;
   const int tid = threadIdx.x;
@@ -307,6 +329,7 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
   const int g0 = static_cast<int>(static_cast<int64_t>(n.G) * blockIdx.x / gridDim.x);
   const int g1 = static_cast<int>(static_cast<int64_t>(n.G) * (blockIdx.x + 1) / gridDim.x);
   const int ng = g1 - g0;
+  const int tu = MODE == 2 ? t + ib : t;  // the step this kernel updates
   // with fewer groups than waves, group q gets waves ceil(16q/ng) ..
   // ceil(16(q+1)/ng) - 1 (2 or 3 waves for 7 groups); else every wave owns
   const bool own = ng >= kWideWaves;
@@ -314,14 +337,12 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
   const int tfirst = own ? wave : (team * kWideWaves + ng - 1) / ng;
   const int m = own ? 1 : (team + 1 == ng ? kWideWaves : ((team + 1) * kWideWaves + ng - 1) / ng) - tfirst;
   const int member = wave - tfirst;
-  // LDS: the staged rows first (a lane record's offset is an LDS address),
-  // then the groups' sums of the two steps and the team slots (with shift =
-  // 0, one step's: the second step's names alias the first's, unused)
+  // LDS: the staged rows first (a lane record's offset is an LDS address)
   uint32_t* ring = smem;                                                                   // [Dl + shift][W32]
-  float* gacc = reinterpret_cast<float*>(smem + static_cast<size_t>(Dl + shift) * W32);   // [g1 - g0][64]
-  float* gacc2 = gacc + static_cast<size_t>(shift) * ng * kGroup;                          // [g1 - g0][64]
-  float(*part)[kGroup] = reinterpret_cast<float(*)[kGroup]>(gacc2 + static_cast<size_t>(ng) * kGroup);  // [16][64]
-  float(*part2)[kGroup] = part + shift * kWideWaves;                                                  // [16][64]
+  float* gacc = reinterpret_cast<float*>(smem + static_cast<size_t>(Dl + shift) * W32);   // [shift + 1][ng][64]
+  const int gstride = ng * kGroup;
+  float* part = gacc + static_cast<size_t>(shift + 1) * gstride;                           // [shift + 1][16][64]
+  constexpr int pstride = kWideWaves * kGroup;
 
   // neuron state of the groups this wave updates, loaded now, used last
   float V[NPW], th[NPW], lam[NPW], rs[NPW], amp[NPW];
@@ -343,35 +364,41 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
       rs[i] = n.reset[j];
       amp[i] = n.amp[j];
       R[i] = n.refr[j];
-      ew[i] = n.ext[row_word(n, t, b, g)];
+      ew[i] = n.ext[row_word(n, tu, b, g)];
     }
   }
-  for (int i = tid; i < ng * kGroup; i += kWideThreads) {
-    if constexpr (MODE == 2)  // the input of this step gathered by the pair's first kernel
-      gacc[i] = n.held[static_cast<size_t>(b) * n.Npad + static_cast<size_t>(g0) * kGroup + i];
+  const size_t hstride = static_cast<size_t>(n.B) * n.Npad;  // held sums of one step
+  const size_t hbase = static_cast<size_t>(b) * n.Npad + static_cast<size_t>(g0) * kGroup;
+  for (int i = tid; i < gstride; i += kWideThreads) {
+    if constexpr (MODE == 2)  // the input of this step gathered by the block's first kernel
+      gacc[i] = n.held[(ib - 1) * hstride + hbase + i];
     else
       gacc[i] = 0.f;
-    if constexpr (MODE == 1) gacc2[i] = 0.f;
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int j = 1; j < KT; ++j) gacc[j * gstride + i] = 0.f;
+    }
   }
 
-  const int phases = MODE == 2 ? 1 : P;  // MODE 2: the delay-1 records of phase 0 only
+  const int phases = MODE == 2 ? 1 : P;  // MODE 2: the short delays of phase 0 only
   for (int p = 0; p < phases; ++p) {
     const int dbase = p * Dl;  // the phase's delays are dbase + 1 .. dbase + Dl
-    const int rows = MODE == 2 ? 1 : min(Dl, n.D - dbase);
-    const int q0 = MODE == 1 && p > 0 ? 0 : 1;  // first staged row
+    // rows q0 .. qhi, row q holding step t - dbase - q at LDS row q + shift - 1
+    const int q0 = MODE == 2 ? 1 - ib : MODE == 1 && p > 0 ? 1 - shift : 1;
+    const int qhi = MODE == 2 ? 0 : min(Dl, n.D - dbase);
+    const int rows = qhi;  // the phase's delays staged (8-byte path)
     // stage the phase's rows: every load of a round is issued before its
     // stores, so a round costs one memory latency, not one per word.  Word
     // i of the phase is (row q0 + i / G, word i mod G); one division per
     // round, then the next word of the thread (1024 further) by adding and
     // carrying, and a word goes to LDS as one 8-byte store.
     uint64_t* ring64 = reinterpret_cast<uint64_t*>(ring);
-    const int staged = (rows + 1 - q0) * n.G;  // words
-    const int lds_end = (rows + 1) * n.G;
-    const int lds_skip = (1 - shift) * n.G;  // row q at LDS word (q - 1 + shift) G; q >= 1 when shift = 0
-    for (int base = 0; base < staged; base += kWideThreads * kWideStage) {
+    const int nrows = qhi - q0 + 1;
+    const int nwords = nrows * n.G;
+    const int at0 = (q0 + shift - 1) * n.G;  // LDS word of row q0 (>= 0)
+    for (int base = 0; base < nwords; base += kWideThreads * kWideStage) {
       uint64_t v[kWideStage];
       int r = (base + tid) / n.G, w = base + tid - r * n.G;
-      int at[kWideStage];  // the word's index q G + w in the staged rows
 #pragma unroll
       for (int q = 0; q < kWideStage; ++q) {
         if (q > 0) {
@@ -381,34 +408,47 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
             ++r;
           }
         }
-        const int row = q0 + r;
-        const int ts = t - dbase - row;
-        at[q] = row * n.G + w;
-        v[q] = (at[q] < lds_end && ts >= 0) ? hist[static_cast<size_t>(ts) * rstride + w] : 0ull;
+        const int ts = t - dbase - (q0 + r);
+        v[q] = (r < nrows && ts >= 0) ? hist[static_cast<size_t>(ts) * rstride + w] : 0ull;
       }
 #pragma unroll
-      for (int q = 0; q < kWideStage; ++q)
-        if (at[q] < lds_end) ring64[at[q] - lds_skip] = v[q];
+      for (int q = 0; q < kWideStage; ++q) {
+        const int i = base + tid + q * kWideThreads;
+        if (i < nwords) ring64[at0 + i] = v[q];
+      }
     }
     __syncthreads();
 
-    float tsum = 0.f, tsum2 = 0.f;  // a team member's share of its group's sums
+    float tsum[NS];  // a team member's share of its group's sums
+#pragma unroll
+    for (int j = 0; j < NS; ++j) tsum[j] = 0.f;
     if constexpr (LANE) {
       const char* ring_bytes = reinterpret_cast<const char*>(ring);
       const uint32_t row_bytes = static_cast<uint32_t>(W32) * sizeof(uint32_t);
-      int isum = 0, isum2 = 0;
+      int isum[NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) isum[j] = 0;
+      constexpr int kPhase = kSecPhase << 6, kLong = kSecLong << 6, kShort = kSecShort << 6, kFrom = kSecFrom << 6;
       if constexpr (MODE == 0) {
-        lane_walk<false>(n, p, 0, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, gacc, gacc2, isum, isum2);
+        lane_walk<1>(n, p, kPhase, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, 0u, gacc, gstride, isum);
       } else if constexpr (MODE == 1) {
-        lane_walk<true>(n, p, 1, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, gacc, gacc2, isum, isum2);
-        if (p == 0)  // the delay-1 records: step t only
-          lane_walk<false>(n, 0, 2, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, gacc, gacc2, isum,
-                           isum2);
-      } else {
-        lane_walk<false>(n, 0, 2, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, gacc, gacc2, isum, isum2);
+        lane_walk<KT>(n, p, kLong, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, 0u, gacc, gstride, isum);
+        if (p == 0) {  // the short delays d < KT: steps t .. t + d - 1
+          if constexpr (KT > 3)
+            lane_walk<3>(n, 0, kShort | 3, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, 0u, gacc, gstride,
+                         isum);
+          if constexpr (KT > 2)
+            lane_walk<2>(n, 0, kShort | 2, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, 0u, gacc, gstride,
+                         isum);
+          lane_walk<1>(n, 0, kShort | 1, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes, 0u, gacc, gstride,
+                       isum);
+        }
+      } else {  // delays 1 .. ib for step t + ib: their words ib rows up
+        lane_walk<1>(n, 0, kFrom | ib, g0, g1, own, team, member, m, lane, ring_bytes, row_bytes,
+                     static_cast<uint32_t>(ib) * row_bytes, gacc, gstride, isum);
       }
-      tsum = static_cast<float>(isum) * n.lscale;
-      tsum2 = static_cast<float>(isum2) * n.lscale;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) tsum[j] = static_cast<float>(isum[j]) * n.lscale;
     } else {
       const uint32_t* ring1 = ring + static_cast<size_t>(shift) * W32;  // row q = 1: the phase's first delay
       // this wave's (group, batch) walk: no barrier until the phase ends, three
@@ -433,7 +473,7 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
           const int d = static_cast<int>((cur[u].meta >> 20) & 63u) + 1;
           const uint32_t pre = cur[u].meta & 0xFFFFFu;
           const bool valid = first + u * 64 < sc.end;
-          const int r = d - dbase - 1;  // row of the phase's staged rows, from row 1
+          const int r = d - dbase - 1;  // row of the phase's staged rows, from row q = 1
           if (!FALLBACK) {
             // every record of the phase lies in its rows; a masked one may not
             const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), rows - 1));
@@ -482,20 +522,18 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
         s1 = s4;
         s2 = s5;
       }
-      tsum = sum;
+      tsum[0] = sum;
     }
     if (!own) {  // a team of m waves per group: the sums meet in LDS
-      part[wave][lane] = tsum;
-      if (MODE == 1) part2[wave][lane] = tsum2;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) part[j * pstride + wave * kGroup + lane] = tsum[j];
       __syncthreads();
       if (member == 0) {
-        float a = gacc[team * kGroup + lane];
-        for (int i = 0; i < m; ++i) a += part[tfirst + i][lane];
-        gacc[team * kGroup + lane] = a;
-        if (MODE == 1) {
-          float a2 = gacc2[team * kGroup + lane];
-          for (int i = 0; i < m; ++i) a2 += part2[tfirst + i][lane];
-          gacc2[team * kGroup + lane] = a2;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          float a = gacc[j * gstride + team * kGroup + lane];
+          for (int i = 0; i < m; ++i) a += part[j * pstride + (tfirst + i) * kGroup + lane];
+          gacc[j * gstride + team * kGroup + lane] = a;
         }
       }
     }
@@ -513,8 +551,11 @@ __global__ __launch_bounds__(kWideThreads) void k_step_wide(const DevNet n, int 
       const size_t sj = static_cast<size_t>(b) * n.Npad + j;
       n.V[sj] = V[i];
       n.ref[sj] = static_cast<uint8_t>(ref[i]);
-      if (lane == 0) n.raster[row_word(n, t, b, g)] = sw;
-      if (MODE == 1) n.held[sj] = gacc2[(g - g0) * kGroup + lane];
+      if (lane == 0) n.raster[row_word(n, tu, b, g)] = sw;
+      if constexpr (MODE == 1) {
+#pragma unroll
+        for (int q = 1; q < KT; ++q) n.held[(q - 1) * hstride + sj] = gacc[q * gstride + (g - g0) * kGroup + lane];
+      }
     }
   }
 }
@@ -523,6 +564,11 @@ bool wide_net(const DevNet& n) {
   return static_cast<size_t>(n.D) * 2 * n.G * sizeof(uint32_t) > kStepRingLimitWide;
 }
 
+// Steps per block of the lane layout: the largest of 4, 2 whose block - 1
+// extra rows and block sets of sums and team slots fit beside Dl >= 1 staged
+// rows, where the phases (if any) are at most kWideMaxPhases and at least
+// block - 1 delays each (a later phase's rows of steps t .. t + block - 2 must
+// all lie before step t); else 1 (no extra rows, no lane records).
 WidePlan wide_plan(const DevNet& n, int cus) {
   WidePlan w;
   w.grid = std::max(1, std::min(cus, n.G));
@@ -533,21 +579,26 @@ WidePlan wide_plan(const DevNet& n, int cus) {
   }
   const size_t row = static_cast<size_t>(2 * n.G) * sizeof(uint32_t);
   const size_t sums = static_cast<size_t>(w.gpw) * kGroup * sizeof(float);
-  // step pairs: two steps' sums and team slots and one row beside the
-  // phase's Dl for the row of one step later, when two rows fit with them;
-  // else one step's sums
-  const size_t dual = (kWideLdsLimit - kWideStaticLds - 2 * (kWidePartLds + sums)) / row;
-  const size_t single = (kWideLdsLimit - kWideStaticLds - kWidePartLds - sums) / row;
-  w.shift = dual >= 2 ? 1 : 0;
-  w.Dl = static_cast<int>(std::min<size_t>(w.shift ? dual - 1 : single, static_cast<size_t>(n.D)));
-  w.P = w.Dl > 0 ? (n.D + w.Dl - 1) / w.Dl : 0;
-  if (w.P > kWideMaxPhases) w.P = 1;  // too many phases: delays above Dl read memory
+  for (int blk : {4, 2, 1}) {
+    const size_t fixed = kWideStaticLds + static_cast<size_t>(blk) * (kWidePartLds + sums);
+    const size_t fit = fixed < kWideLdsLimit ? (kWideLdsLimit - fixed) / row : 0;
+    const int Dl = static_cast<int>(std::min<size_t>(fit >= static_cast<size_t>(blk) ? fit - (blk - 1) : 0,
+                                                     static_cast<size_t>(n.D)));
+    const int P = Dl > 0 ? (n.D + Dl - 1) / Dl : 0;
+    const bool ok = blk == 1 || (Dl >= 1 && P <= kWideMaxPhases && (P == 1 || Dl >= blk - 1));
+    if (!ok) continue;
+    w.block = blk;
+    w.shift = blk - 1;
+    w.Dl = Dl;
+    w.P = P > kWideMaxPhases ? 1 : P;  // too many phases: delays above Dl read memory
+    break;
+  }
   return w;
 }
 
 static size_t wide_lds(const DevNet& n, const WidePlan& w, int Dl) {
   return static_cast<size_t>(Dl + w.shift) * 2 * n.G * sizeof(uint32_t) +
-         (1 + w.shift) * (static_cast<size_t>(w.gpw) * kGroup * sizeof(float) + kWidePartLds);
+         static_cast<size_t>(w.block) * (static_cast<size_t>(w.gpw) * kGroup * sizeof(float) + kWidePartLds);
 }
 
 // Phases come from the layout (n.phases, n.phase_rows); a layout without
@@ -559,16 +610,18 @@ hipError_t prepare_wide_kernel(const DevNet& n, int cus) {
   const int Dl = wide_rows_of(n, w);
   if (Dl < 1 || wide_lds(n, w, Dl) + kWideStaticLds > kWideLdsLimit) return hipErrorInvalidValue;
   const int bytes = static_cast<int>(wide_lds(n, w, Dl));
-  const void* fns[] = {reinterpret_cast<const void*>(&k_step_wide<false, 1, false, 0>),
-                       reinterpret_cast<const void*>(&k_step_wide<true, 1, false, 0>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, false, 0>),
-                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw, false, 0>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 0>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 0>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 1>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 1>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 2>),
-                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 2>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_step_wide<false, 1, false, 0, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, 1, false, 0, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, false, 0, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<true, kWideNpw, false, 0, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 0, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 0, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 1, 2>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 1, 2>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 1, 4>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 1, 4>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, 1, true, 2, 1>),
+                       reinterpret_cast<const void*>(&k_step_wide<false, kWideNpw, true, 2, 1>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -585,11 +638,11 @@ hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) 
   const bool fallback = P == 1 && Dl < n.D;
   const dim3 grid(w.grid, n.B), block(kWideThreads);
   const size_t lds = wide_lds(n, w, Dl);
-  // lane records address the staged rows: only when every delay is staged
-  // (from LDS row 1)
-  const bool lane = n.lrecs != nullptr && !fallback && w.shift == 1;
+  // lane records address the staged rows: only when every delay is staged,
+  // from the layout's block
+  const bool lane = n.lrecs != nullptr && !fallback && w.block >= 2 && n.lblock == w.block;
 #define SN_WIDE(FB, NPW, LN) \
-  hipLaunchKernelGGL((k_step_wide<FB, NPW, LN, 0>), grid, block, lds, s, n, t, Dl, P, w.shift)
+  hipLaunchKernelGGL((k_step_wide<FB, NPW, LN, 0, 1>), grid, block, lds, s, n, t, Dl, P, w.shift, 0)
   const int key = (fallback ? 1 : 0) + (w.gpw <= kWideWaves ? 0 : 2) + (lane ? 4 : 0);
   switch (key) {
     case 0: SN_WIDE(false, 1, false); break;
@@ -603,28 +656,36 @@ hipError_t launch_step_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) 
   return hipGetLastError();
 }
 
-bool wide_pairs(const DevNet& n, int cus) {
-  if (!n.lrecs || !n.lgsplit || !n.held) return false;
+int wide_block(const DevNet& n, int cus) {
+  if (!n.lrecs || !n.lsec || !n.held) return 1;
   const WidePlan w = wide_plan(n, cus);
   const int Dl = wide_rows_of(n, w);
   const int P = n.phases > 1 ? n.phases : 1;
-  return Dl >= 1 && w.shift == 1 && !(P == 1 && Dl < n.D) && wide_lds(n, w, Dl) + kWideStaticLds <= kWideLdsLimit;
+  const bool ok = w.block >= 2 && n.lblock == w.block && Dl >= 1 && !(P == 1 && Dl < n.D) &&
+                  (P == 1 || Dl >= w.block - 1) && wide_lds(n, w, Dl) + kWideStaticLds <= kWideLdsLimit;
+  return ok ? w.block : 1;
 }
 
-hipError_t launch_pair_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) {
-  if (!wide_pairs(n, cus)) return hipErrorInvalidValue;
+hipError_t launch_block_wide(const DevNet& n, int32_t t, int cus, hipStream_t s) {
+  const int blk = wide_block(n, cus);
+  if (blk < 2) return hipErrorInvalidValue;
   const WidePlan w = wide_plan(n, cus);
   const int Dl = wide_rows_of(n, w);
   const int P = n.phases > 1 ? n.phases : 1;
   if (P > 1 && Dl * P < n.D) return hipErrorInvalidValue;  // phases must cover every delay
   const dim3 grid(w.grid, n.B), block(kWideThreads);
   const size_t lds = wide_lds(n, w, Dl);
-  if (w.gpw <= kWideWaves) {
-    hipLaunchKernelGGL((k_step_wide<false, 1, true, 1>), grid, block, lds, s, n, t, Dl, P, 1);
-    hipLaunchKernelGGL((k_step_wide<false, 1, true, 2>), grid, block, lds, s, n, t + 1, Dl, P, 1);
+  const bool one = w.gpw <= kWideWaves;
+  if (blk == 4) {
+    if (one) hipLaunchKernelGGL((k_step_wide<false, 1, true, 1, 4>), grid, block, lds, s, n, t, Dl, P, 3, 0);
+    else hipLaunchKernelGGL((k_step_wide<false, kWideNpw, true, 1, 4>), grid, block, lds, s, n, t, Dl, P, 3, 0);
   } else {
-    hipLaunchKernelGGL((k_step_wide<false, kWideNpw, true, 1>), grid, block, lds, s, n, t, Dl, P, 1);
-    hipLaunchKernelGGL((k_step_wide<false, kWideNpw, true, 2>), grid, block, lds, s, n, t + 1, Dl, P, 1);
+    if (one) hipLaunchKernelGGL((k_step_wide<false, 1, true, 1, 2>), grid, block, lds, s, n, t, Dl, P, 1, 0);
+    else hipLaunchKernelGGL((k_step_wide<false, kWideNpw, true, 1, 2>), grid, block, lds, s, n, t, Dl, P, 1, 0);
+  }
+  for (int i = 1; i < blk; ++i) {
+    if (one) hipLaunchKernelGGL((k_step_wide<false, 1, true, 2, 1>), grid, block, lds, s, n, t, Dl, P, blk - 1, i);
+    else hipLaunchKernelGGL((k_step_wide<false, kWideNpw, true, 2, 1>), grid, block, lds, s, n, t, Dl, P, blk - 1, i);
   }
   return hipGetLastError();
 }
@@ -637,17 +698,17 @@ static hipError_t device_cus_wide(int& cus) {
 }
 
 // the per-step path of a net runs this kernel exactly when wide_net holds
-bool step_pairs(const DevNet& n) {
-  if (!wide_net(n)) return false;
+int step_block(const DevNet& n) {
+  if (!wide_net(n)) return 1;
   int cus = 0;
-  if (device_cus_wide(cus) != hipSuccess) return false;
-  return wide_pairs(n, cus);
+  if (device_cus_wide(cus) != hipSuccess) return 1;
+  return wide_block(n, cus);
 }
 
-hipError_t launch_step_pair(const DevNet& n, int32_t t, hipStream_t s) {
+hipError_t launch_step_block(const DevNet& n, int32_t t, hipStream_t s) {
   int cus = 0;
   const hipError_t e = device_cus_wide(cus);
-  return e != hipSuccess ? e : launch_pair_wide(n, t, cus, s);
+  return e != hipSuccess ? e : launch_block_wide(n, t, cus, s);
 }
 
 }  // namespace snmi

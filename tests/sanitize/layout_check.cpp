@@ -154,14 +154,15 @@ static void check_layout(const Net& net, int32_t phase_rows) {
   }
 }
 
-// The lane-only layout of the wide kernel and its 4-byte lane records: every
-// section whole rows, every record in its post's lane, and each lane record
-// naming the LDS word and bit of its source in the phase's staged rows, with
-// its weight's numerator (fillers: k = 0).
-static void check_lane_layout(const Net& net, int32_t phase_rows) {
+// The lane-only layout of the wide kernel for blocks of `block` steps and its
+// 4-byte lane records: every section whole rows (the phases of the delays >=
+// block, then one section per delay block - 1 .. 1), every record in its
+// post's lane, and each lane record naming the LDS word and bit of its source
+// in the phase's staged rows, with its weight's numerator (fillers: k = 0).
+static void check_lane_layout(const Net& net, int32_t phase_rows, int32_t block) {
   const int64_t nnz = static_cast<int64_t>(net.pre.size());
   HostLayout L = build_layout(net.n, nnz, net.pre.data(), net.post.data(), net.w.data(), net.d.data(), net.D,
-                              phase_rows, true);
+                              phase_rows, true, block);
   CHECK(!L.too_large, "lane layout: unexpected too_large");
   const int32_t G = (net.n + kGroup - 1) / kGroup;
   const int32_t P = L.phases;
@@ -172,10 +173,11 @@ static void check_lane_layout(const Net& net, int32_t phase_rows) {
   const int64_t row = kGroup;
   std::vector<int> seen(static_cast<size_t>(nnz), 0);
   for (int32_t g = 0; g < G; ++g) {
-    // sections: phases P-1 .. 0 of the delay >= 2 records, then the delay-1 records
+    // sections: phases P-1 .. 0 of the delay >= block records, then delays block - 1 .. 1
     std::vector<int32_t> bound;
     for (int32_t p = P - 1; p >= 0; --p) bound.push_back(L.wsec[static_cast<size_t>(g) * P + p]);
-    bound.push_back(L.gsplit[g]);
+    for (int32_t d = block - 1; d >= 1; --d) bound.push_back(L.ssec[static_cast<size_t>(g) * (block - 1) + d - 1]);
+    CHECK(L.gsplit[g] == bound.back(), "lane group %d: delay-1 section", g);
     bound.push_back(L.gptr[g + 1]);
     CHECK(bound[0] == L.gptr[g], "lane group %d: first section", g);
     for (size_t q = 0; q + 1 < bound.size(); ++q)
@@ -185,25 +187,28 @@ static void check_lane_layout(const Net& net, int32_t phase_rows) {
       const int32_t k = L.src[i];
       const uint32_t off = (c >> 5) & (kLaneMaxOffset - 1u);
       CHECK(static_cast<int32_t>(L.recs[i].meta >> 26) == (i - L.gptr[g]) % kGroup, "lane record %d off its lane", i);
-      // every record, filler or not, names a word of staged row 1 or below
-      // (the first kernel of a step pair also reads the word one row up)
-      CHECK(off >= 2u * G * 4u, "lane record %d: offset above row 1", i);
+      // every record, filler or not, names a word of staged row block - 1 or
+      // below (the kernels of a block read up to block - 1 rows higher)
+      CHECK(off >= static_cast<uint32_t>(block - 1) * 2u * G * 4u, "lane record %d: offset above row %d", i,
+            block - 1);
       if (k < 0) {
         CHECK((c >> 24) == 0, "filler %d: k", i);
         continue;
       }
       ++seen[k];
       const int32_t pre = net.pre[k], d = net.d[k];
-      // delay 1 exactly in the last section, delays >= 2 of phase p in phase p's
+      // a short delay in its own section, delays >= block of phase p in phase p's
       size_t sec = 0;
       while (bound[sec + 1] <= i) ++sec;
-      if (sec + 1 == bound.size() - 1) {
-        CHECK(d == 1, "lane record %d: delay %d in the delay-1 section", i, d);
+      if (static_cast<int32_t>(sec) >= P) {
+        const int32_t ds = P + block - 1 - static_cast<int32_t>(sec);
+        CHECK(d == ds, "lane record %d: delay %d in the section of delay %d", i, d, ds);
       } else {
         const int32_t ph = P - 1 - static_cast<int32_t>(sec);
-        CHECK(d >= 2 && (P == 1 || (d - 1) / phase_rows == ph), "lane record %d: delay %d in phase %d", i, d, ph);
+        CHECK(d >= block && (P == 1 || (d - 1) / phase_rows == ph), "lane record %d: delay %d in phase %d", i, d, ph);
       }
-      const uint32_t row = (P > 1 ? static_cast<uint32_t>((d - 1) % phase_rows) : static_cast<uint32_t>(d - 1)) + 1u;
+      const uint32_t row = (P > 1 ? static_cast<uint32_t>((d - 1) % phase_rows) : static_cast<uint32_t>(d - 1)) +
+                           static_cast<uint32_t>(block - 1);
       CHECK(off % 4 == 0 && off / 4 == row * 2u * G + static_cast<uint32_t>(pre) / 32u, "lane record %d: offset", i);
       CHECK((c & 31u) == static_cast<uint32_t>(pre) % 32u, "lane record %d: bit", i);
       const float wk = static_cast<float>(static_cast<int8_t>(c >> 24)) * scale;
@@ -244,9 +249,12 @@ int main() {
       check_layout(net, pr);
       if (g_fail) return;
       ++cases;
-      check_lane_layout(net, pr);
-      if (g_fail) return;
-      ++cases;
+      for (int32_t block : {2, 4}) {
+        if (pr > 0 && pr < block - 1) continue;  // a later phase must start at a delay >= block
+        check_lane_layout(net, pr, block);
+        if (g_fail) return;
+        ++cases;
+      }
     }
   };
   {  // empty nets
