@@ -197,7 +197,7 @@ def bench_single(args, net, kind):
         # phases (k_step_wide) once its 2*D words per 64-neuron group pass 64 KiB
         wide = 8 * net.max_delay * -(-net.n // 64) > 64 * 1024
         kernel = {"persist": "k_sim (multi-slice)", "small": "k_sim (one slice)",
-                  "step": "k_step_wide (step pairs)" if wide else "k_step", "push": "k_push"}.get(path, path)
+                  "step": "k_step_wide (blocks of 4 steps)" if wide else "k_step", "push": "k_push"}.get(path, path)
         if kind == "stdp":
             kernel = "k_step + k_stdp (per step)"
         traffic = None

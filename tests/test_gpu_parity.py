@@ -207,8 +207,9 @@ def test_wide_step_lane_records(gpu, oracle, n, p, D, trials):
     in its lane, no hub: the lane-only copy is kept): two delay phases with
     2 trials; every delay staged at once; more than 16 groups per workgroup
     (each wave owns groups) with two phases; empty sections throughout.
-    Runs of 1, 40 and 49 steps: a single step, step pairs, and pairs
-    followed by a single step."""
+    Runs of 1, 40 and 49 steps: a single step, blocks of steps (of 4; of 2
+    at N = 270,000, whose LDS holds no block of 4), and blocks followed by a
+    single step."""
     net = wl.large_sparse(60 + D, n=n, p=p, steps=90, max_delay=D)
     net = _with_gaps(dataclasses.replace(net, trials=trials, ext=np.concatenate([net.ext] * trials)))
     if trials > 1:
