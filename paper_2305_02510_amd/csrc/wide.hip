@@ -3,12 +3,14 @@
 // synaptic input of §2.1's update summed over the pull records of every
 // post-neuron group, followed by the fused neuron update.
 //
-// One launch per step, or two per step pair (see MODE below: records of
-// delay >= 2 read once for two steps).  Workgroup (w, b) owns the contiguous groups
+// One launch per step, or K launches per block of K steps (see MODE below:
+// records of delay >= K read once for K steps).  Workgroup (w, b) owns the
+// contiguous groups
 // [g0, g1) of trial b.  The delays are cut into phases of Dl delays (Dl =
 // as many history rows as fit in LDS beside the sums); the layout orders the
 // delay >= 2 records of every group by phase (phases P-1 .. 1, then phase 0
-// running on into the delay-1 records).  For each phase the workgroup copies
+// running on into the delay-1 records; lane layouts: the delays >= K, then a
+// section for each delay K - 1 .. 1).  For each phase the workgroup copies
 // the raster rows of that phase's delays into LDS once, then streams the
 // phase's records of all its groups, finding every source bit in LDS.
 // Looking each bit up in the raster in memory instead costs one scattered L2
@@ -31,7 +33,7 @@
 //
 // LANE: when every delay is staged (phases cover D) the net may also hold a
 // lane-only copy of its layout (no overflow: every record in its post's lane;
-// the delay-1 records in a section of their own after the phases)
+// the short delays in sections of their own after the phases)
 // as 4-byte lane records that carry the LDS offset of their source word, the
 // source's bit and an int8 weight numerator, every section whole rows of
 // 64.  The kernel then streams those, half the bytes of the
