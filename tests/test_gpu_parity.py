@@ -201,15 +201,16 @@ def _with_gaps(net):
                                delay=net.delay[keep], name=net.name + "_gaps")
 
 
-@pytest.mark.parametrize("n,p,D,trials", [(20_000, 0.002, 64, 2), (33_000, 0.001, 20, 1), (270_000, 0.0001, 8, 1)])
+@pytest.mark.parametrize("n,p,D,trials", [(20_000, 0.002, 64, 2), (33_000, 0.001, 20, 1), (270_000, 0.0001, 8, 1),
+                                          (180_000, 0.00015, 3, 1)])
 def test_wide_step_lane_records(gpu, oracle, n, p, D, trials):
     """The wide per-step kernel on 4-byte lane records (every post's synapses
     in its lane, no hub: the lane-only copy is kept): two delay phases with
     2 trials; every delay staged at once; more than 16 groups per workgroup
     (each wave owns groups) with two phases; empty sections throughout.
     Runs of 1, 40 and 49 steps: a single step, blocks of steps (of 4; of 2
-    at N = 270,000, whose LDS holds no block of 4), and blocks followed by a
-    single step."""
+    at N = 270,000, whose LDS holds no block of 4; of 4 with every delay
+    below 4 at N = 180,000, D = 3), and blocks followed by a single step."""
     net = wl.large_sparse(60 + D, n=n, p=p, steps=90, max_delay=D)
     net = _with_gaps(dataclasses.replace(net, trials=trials, ext=np.concatenate([net.ext] * trials)))
     if trials > 1:
