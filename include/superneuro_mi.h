@@ -254,8 +254,11 @@ typedef struct {
  * applies the rule after every step; the weights change in place
  * (sn_reset_state does not restore them; sn_load_weights_delays does), and
  * the event-driven path refuses to run (SN_ESTATE) until the weights are
- * loaded again.  Errors: SN_ESTATE, SN_ERANGE (window, trials), SN_EINVAL
- * (non-finite entries, w_min > w_max). */
+ * loaded again.  Turning it on also drops the 4-byte copies of the records
+ * that some kernels read, so that after it is turned off every other path
+ * runs with the learned weights (until sn_load_weights_delays rebuilds them).
+ * Errors: SN_ESTATE, SN_ERANGE (window, trials), SN_EINVAL (non-finite
+ * entries, w_min > w_max), SN_EDEVICE. */
 sn_status sn_set_stdp(sn_net* net, const sn_stdp_desc* desc);
 
 /* Copies the current synapse weights to w [nnz], in the order of the last

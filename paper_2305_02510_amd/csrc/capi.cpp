@@ -1364,6 +1364,29 @@ sn_status sn_read_state_device(sn_net* n, float* V, uint8_t* refractory_left) {
   return SN_OK;
 }
 
+// Plasticity changes the weights of the 8-byte records in place; the 4-byte
+// copies (compact records of the persistent and batch kernels, lane records
+// of the wide kernel) keep the loaded ones.  Turning plasticity on drops them,
+// so every path reads the 8-byte records from then on (reloading the synapses
+// builds them again).
+static sn_status drop_weight_copies(sn_net* n) {
+  if (!n->crecs && !n->lrecs) return SN_OK;
+  SN_HIP(n, hipStreamSynchronize(n->stream));  // queued work may still read them
+  drop_graph(n);
+  for (void** p : {&n->crecs, &n->lrecs, &n->lgptr, &n->lwsec}) {
+    dev_free(n, *p);
+    *p = nullptr;
+  }
+  n->d.crecs = nullptr;
+  n->d.lrecs = nullptr;
+  n->d.lgptr = nullptr;
+  n->d.lwsec = nullptr;
+  n->d.lsec = nullptr;
+  n->d.held = nullptr;
+  n->d.lblock = 0;
+  return SN_OK;
+}
+
 sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
   sn_status st = check_usable(n);
   if (st != SN_OK) return st;
@@ -1395,6 +1418,8 @@ sn_status sn_set_stdp(sn_net* n, const sn_stdp_desc* desc) {
     if (!n->stdp_hist) return fail(SN_ENOMEM, "cannot allocate the spike-history words");
   }
   a.hist = n->stdp_hist;
+  st = drop_weight_copies(n);
+  if (st != SN_OK) return st;
   stdp_chunks(n->layout.max_group_records, a.chunk, a.chunks);
   SN_HIP(n, prepare_stdp_kernel());
   n->stdp = a;

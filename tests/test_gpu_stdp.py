@@ -106,6 +106,34 @@ def test_stdp_rules_of_use(gpu, oracle):
     g.close()
 
 
+@pytest.mark.parametrize("n,p,D", [(3000, 0.02, 16), (40_000, 0.0005, 16)])
+def test_learned_weights_on_every_path(gpu, oracle, n, p, D):
+    """After plasticity has changed the weights and is turned off, the paths
+    that read 4-byte copies of the records (persistent kernel: compact
+    records at N = 3000; wide per-step kernel: lane records at N = 40,000)
+    run with the learned weights: they continue the run exactly as the
+    per-step path that learned them (8-byte records) does."""
+    net = wl.large_sparse(620 + n % 97, n=n, p=p, steps=100, max_delay=D)
+    other = "persist" if n < 10_000 else "step"
+    ref = "step" if other == "persist" else "persist"
+    runs = {}
+    for second in (ref, other):
+        g = gpu.from_workload(net)
+        g.set_stdp(4, LTP, LTD, -1.0, 1.5)
+        g.set_path("step")
+        g.run(40)
+        learned = g.read_weights()
+        g.stdp_off()
+        g.set_path(second)
+        g.run(60)
+        assert g.progress[1] == second
+        runs[second] = (g.read_raster(0, 100), *g.read_state(), learned)
+        g.close()
+    assert not np.array_equal(runs[ref][3], net.weight.astype(np.float32)), "the rule changed no weight"
+    for a, b in zip(runs[ref], runs[other]):
+        assert np.array_equal(a, b)
+
+
 def test_batch_refuses_plasticity(gpu, oracle):
     """A batch does not apply the rule, so it refuses a net with plasticity
     on, both when planned and when the rule is turned on afterwards."""
