@@ -77,7 +77,7 @@ __device__ __forceinline__ void wide_load(const DevNet& n, int base, int end, in
 constexpr int kSecPhase = 0, kSecLong = 1, kSecShort = 2, kSecFrom = 3;
 template <bool LANE>
 __device__ __forceinline__ void wide_range(const DevNet& n, int g, int p, int kind, int d, int& beg, int& end) {
-    if (!LANE) {
+  if (!LANE) {
     if (n.phases <= 1) {
       beg = n.gptr[g];
       end = n.gptr[g + 1];
